@@ -1,0 +1,224 @@
+"""Pins for the CPU oracle: checks against facts fixed outside the oracle.
+
+Each group targets a class of plausible mistakes:
+* hand-worked examples (tests/golden/handworked.json) -- wrong sum, wrong
+  wrap, transposed operand;
+* Python-integer brute force on tiny random and extreme inputs -- any
+  indexing, pitch or overflow slip in the C loops;
+* closed forms (column selection, scaled column, row sums, all-ones and
+  all-0xFF matrices, the 2^31 accumulator case at C = 131072);
+* invariants (linearity, batch column = single answer, row permutation,
+  hint = batch on A, row update = full recompute);
+* the LWE round trip, checked exactly against numpy integer arithmetic
+  (a - H s = D e + Delta D[:, i]) and by decoding the queried column;
+* decode rounding boundaries.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "handworked.json")
+M32 = 1 << 32
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- golden
+def test_handworked_answer(golden):
+    for case in golden["answer"]:
+        D = np.array(case["D"], dtype=np.uint8)
+        q = np.array(case["q"], dtype=np.uint32)
+        assert oracle.answer(D, q).tolist() == case["a"], case["derivation"]
+
+
+def test_handworked_batch(golden):
+    for case in golden["answer_batch"]:
+        D = np.array(case["D"], dtype=np.uint8)
+        Q = np.array(case["Q"], dtype=np.uint32)
+        assert oracle.answer_batch(D, Q).tolist() == case["out"], case["derivation"]
+
+
+def test_handworked_lwe(golden):
+    for case in golden["lwe_round_trip"]:
+        A = np.array(case["A"], dtype=np.uint32)
+        s = np.array(case["s"], dtype=np.uint32)
+        D = np.array(case["D"], dtype=np.uint8)
+        q = oracle.lwe_query(A, s, case["e"], case["col"])
+        assert q.tolist() == case["q"]
+        H = oracle.hint(D, A)
+        assert H.tolist() == case["H"]
+        a = oracle.answer(D, q)
+        assert a.tolist() == case["a"]
+        assert oracle.matvec_u32(H, s).tolist() == case["Hs"]
+        assert oracle.lwe_decode(a, H, s).tolist() == case["decoded"]
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_force_random(seed):
+    g = np.random.default_rng(seed)
+    R = int(g.integers(1, 18))
+    C = int(g.integers(1, 18))
+    B = int(g.integers(1, 6))
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    Q = g.integers(0, M32, size=(C, B), dtype=np.uint32)
+    assert oracle.answer_batch(D, Q).tolist() == oracle.brute_answer_batch(D.tolist(), Q.tolist())
+    for b in range(B):
+        assert oracle.answer(D, Q[:, b]).tolist() == oracle.brute_answer(D.tolist(), Q[:, b].tolist())
+
+
+@pytest.mark.parametrize("dval,qval", [(0, 0), (255, 0xFFFFFFFF), (0x80, 0x80808080),
+                                       (255, 0), (0, 0xFFFFFFFF), (1, 0x7FFFFFFF)])
+def test_brute_force_extremes(dval, qval):
+    R, C, B = 5, 17, 3
+    D = np.full((R, C), dval, dtype=np.uint8)
+    Q = np.full((C, B), qval, dtype=np.uint32)
+    D[0, 0] ^= 0x5A   # break the symmetry so a transposed operand shows
+    Q[C - 1, B - 1] ^= 0xDEADBEEF
+    assert oracle.answer_batch(D, Q).tolist() == oracle.brute_answer_batch(D.tolist(), Q.tolist())
+
+
+def test_subset_rows_match_brute():
+    g = np.random.default_rng(7)
+    D = g.integers(0, 256, size=(13, 9), dtype=np.uint8)
+    Q = g.integers(0, M32, size=(9, 4), dtype=np.uint32)
+    rows = [12, 0, 5]
+    full = oracle.brute_answer_batch(D.tolist(), Q.tolist())
+    assert oracle.answer_batch(D, Q, rows=rows).tolist() == [full[r] for r in rows]
+
+
+# ---------------------------------------------------------------- closed forms
+def test_closed_forms():
+    g = np.random.default_rng(1)
+    R, C = 37, 29
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    for j in (0, 13, C - 1):
+        e = np.zeros(C, dtype=np.uint32)
+        e[j] = 1
+        assert np.array_equal(oracle.answer(D, e), D[:, j].astype(np.uint32))
+        e[j] = oracle.DELTA
+        assert np.array_equal(oracle.answer(D, e), D[:, j].astype(np.uint32) << 24)
+    ones = np.ones(C, dtype=np.uint32)
+    assert np.array_equal(oracle.answer(D, ones), D.astype(np.uint64).sum(axis=1).astype(np.uint32))
+    q = g.integers(0, M32, size=C, dtype=np.uint32)
+    assert not oracle.answer(np.zeros((R, C), np.uint8), q).any()
+    expect = (128 * int(q.astype(np.uint64).sum())) % M32
+    assert (oracle.answer(np.full((R, C), 0x80, np.uint8), q) == expect).all()
+
+
+@pytest.mark.parametrize("C", [1, 1000, 131072])
+def test_closed_form_all_ff(C):
+    D = np.full((3, C), 255, dtype=np.uint8)
+    q = np.full(C, 0xFFFFFFFF, dtype=np.uint32)
+    assert (oracle.answer(D, q) == (M32 - 255 * C) % M32).all()
+
+
+def test_accumulator_wrap_closed_forms():
+    """C = 131072: sums pass 2^32 many times; the answer is the exact value mod 2^32."""
+    C = 131072
+    g = np.random.default_rng(3)
+    q = g.integers(0, M32, size=C, dtype=np.uint32)
+    D = np.zeros((2, C), dtype=np.uint8)
+    D[1] = 255
+    a = oracle.answer(D, q)
+    assert a[0] == 0
+    assert a[1] == (255 * int(q.astype(np.uint64).sum())) % M32
+    # uint8 x uint8 limbs at their maximum: 0xFF x 0x000000FF over C terms
+    qq = np.full(C, 0xFF, dtype=np.uint32)
+    assert oracle.answer(D, qq)[1] == (255 * 255 * C) % M32
+
+
+# ---------------------------------------------------------------- invariants
+def test_invariants():
+    g = np.random.default_rng(11)
+    R, C, B = 23, 41, 6
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    Q = g.integers(0, M32, size=(C, B), dtype=np.uint32)
+    out = oracle.answer_batch(D, Q)
+    for b in range(B):
+        assert np.array_equal(out[:, b], oracle.answer(D, Q[:, b]))
+    # linearity over Z/2^32
+    x, y = Q[:, 0], Q[:, 1]
+    lhs = oracle.answer(D, (x.astype(np.uint64) * 3 + y).astype(np.uint32))
+    rhs = (oracle.answer(D, x).astype(np.uint64) * 3 + oracle.answer(D, y)).astype(np.uint32)
+    assert np.array_equal(lhs, rhs)
+    # row permutation of D permutes the answer
+    perm = g.permutation(R)
+    assert np.array_equal(oracle.answer(D[perm], x), oracle.answer(D, x)[perm])
+    # hint is the batch product on A
+    A = g.integers(0, M32, size=(C, 8), dtype=np.uint32)
+    assert np.array_equal(oracle.hint(D, A), oracle.answer_batch(D, A))
+    # Freivalds accepts the right product and rejects a one-entry error
+    assert oracle.freivalds(D, Q, out, trials=8)
+    bad = out.copy()
+    bad[5, 3] ^= 1 << 31
+    assert not oracle.freivalds(D, Q, bad, trials=16)
+
+
+def test_matvec_u32_against_numpy():
+    g = np.random.default_rng(5)
+    M = g.integers(0, M32, size=(31, 77), dtype=np.uint32)
+    x = g.integers(0, M32, size=77, dtype=np.uint32)
+    # numpy's uint64 product wraps mod 2^64, a multiple of 2^32
+    ref = (M.astype(np.uint64) @ x.astype(np.uint64)).astype(np.uint32)
+    assert np.array_equal(oracle.matvec_u32(M, x), ref)
+
+
+def test_update_rows_equals_recompute():
+    g = np.random.default_rng(9)
+    R, C, n = 40, 33, 16
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    A = g.integers(0, M32, size=(C, n), dtype=np.uint32)
+    rows = workload.distinct_rows(g, R, 5)
+    new = g.integers(0, 256, size=(5, C), dtype=np.uint8)
+    D2 = oracle.update_rows(D, rows, new)
+    assert np.array_equal(D2[rows], new)
+    untouched = np.setdiff1d(np.arange(R), rows)
+    assert np.array_equal(D2[untouched], D[untouched])
+    H = oracle.hint(D, A)
+    H2 = H.copy()
+    H2[rows] = oracle.hint(D2, A, rows=rows)
+    assert np.array_equal(H2, oracle.hint(D2, A))
+
+
+# ---------------------------------------------------------------- LWE round trip
+def _lwe_case(R, C, n, seed):
+    g = workload.rng(seed)
+    D = workload.db_bytes(g, R, C)
+    A = workload.uniform_u32(g, (C, n))
+    dr = workload.lwe_draws(g, C, n, 1)
+    return D, A, dr.s[0], dr.e[0], int(dr.col[0])
+
+
+@pytest.mark.parametrize("R,C,n", [(1024, 1024, 1024), (64, 4096, 256), (300, 77, 32)])
+def test_lwe_round_trip_exact(R, C, n):
+    D, A, s, e, col = _lwe_case(R, C, n, workload.SEED_BASE)
+    q = oracle.lwe_query(A, s, e, col)
+    a = oracle.answer(D, q)
+    H = oracle.hint(D, A)
+    # exact identity over the integers mod 2^32, checked with numpy int64
+    De = D.astype(np.int64) @ e.astype(np.int64)
+    expect = (De + oracle.DELTA * D[:, col].astype(np.int64)) % M32
+    got = (a.astype(np.int64) - oracle.matvec_u32(H, s).astype(np.int64)) % M32
+    assert np.array_equal(got, expect)
+    assert np.array_equal(oracle.lwe_decode(a, H, s), D[:, col])
+
+
+def test_decode_rounding_boundaries():
+    """Noise in [-2^23, 2^23) decodes to m; +2^23 rounds up to m+1."""
+    H = np.zeros((6, 1), dtype=np.uint32)
+    s = np.zeros(1, dtype=np.uint32)
+    m = np.array([0, 7, 255, 0, 100, 255], dtype=np.int64)
+    noise = np.array([(1 << 23) - 1, -(1 << 23), 0, -1, 1 << 23, (1 << 23) - 1])
+    a = ((m << 24) + noise) % M32
+    dec = oracle.lwe_decode(a.astype(np.uint32), H, s)
+    assert dec.tolist() == [0, 7, 255, 0, 101, 255]
