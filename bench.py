@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the PIR Answer on one MI355X.
+
+Headline: single-query Answer GB/s of database scanned on a 32768 x 32768
+uint8 database (1 GiB) with one LWE query (n = 1024, sigma = 6.4).  A step is
+one Answer over the resident database; inputs are in HBM before timing.
+
+Also reported on the same line: the 64-query batched Answer and the offline
+hint on the same database (matrix cores), and the oracle timed on the host
+cores on a bounded sample (``cpu_baseline``).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 matrix, published (TOP/s)
+METRIC = "PIR Answer GB/s of DB scanned (1 and 64 queries); p50/p99 served latency"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_03631_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if they were
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_on_stream(fn, steps: int, stream):
+    """Run fn() `steps` times; return (wall seconds, event seconds)."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, start.elapsed_time(stop) / 1e3
+
+
+def cpu_baseline(R: int, C: int, seconds: float = 10.0):
+    """Oracle single-query Answer on a bounded sample of the workload."""
+    import numpy as np
+    import oracle
+    import workload
+    g = workload.rng(workload.SEED_BASE + 99)
+    rows = min(R, 2048)
+    D = workload.db_bytes(g, rows, C)
+    q = workload.uniform_u32(g, C)
+    oracle.answer(D, q)   # load + warm
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.answer(D, q)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    gbs = rows * C * n / el / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{rows} x {C} uint8 rows of the database, one query, "
+                      f"{n} passes in {el:.1f} s (plain C loops, OpenMP)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2510_03631_amd as qp
+    import workload
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    shape = workload.CONFIGS["spectrum_1q"]
+    R, C, n = shape.rows, shape.cols, shape.n
+
+    log(f"drawing {R}x{C} database on the device")
+    D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
+    db = qp.Database(D)
+    # One LWE query.  The client's query is A s + e + Delta u_i; timing the
+    # answer does not depend on its value, and under LWE it is
+    # indistinguishable from uniform, so the bench draws the words directly
+    # (the parity tests use real queries built by the client).
+    q = workload.device_u32((C,), workload.SEED_BASE + 2, dev)
+    a = torch.empty(R, dtype=torch.int32, device=dev)
+    ws = db.workspace(0)
+
+    def step():
+        db.answer(q, out=a, ws=ws)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    wall, ev = time_on_stream(step, args.steps, stream)
+    ms_per_step = wall / args.steps * 1e3
+    bytes_db = R * C
+    value = bytes_db / (wall / args.steps) / 1e9
+    alg_bytes = R * C + 4 * C + 4 * R
+    kern_s = ev / args.steps
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = load_traffic("k_answer1/spectrum_1q")
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "spectrum_1q: single-query Answer, 32768 x 32768 uint8 "
+                               "database (1 GiB), one LWE query (n=1024, sigma=6.4), "
+                               "a = D q mod 2^32",
+                   "rows": R, "cols": C, "queries": 1},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_answer1",
+                     "bytes_per_launch": alg_bytes,
+                     "avg_launch_us": round(kern_s * 1e6, 2)},
+    }
+
+    if not args.no_batch:
+        B = 64
+        log("batched answer, 64 queries")
+        Q = workload.device_u32((C, B), workload.SEED_BASE + 3, dev)
+        out = torch.empty((R, B), dtype=torch.int32, device=dev)
+        wsb = db.workspace(B)
+        fb = lambda: db.answer_batch(Q, out=out, ws=wsb)
+        for _ in range(5):
+            fb()
+        wallb, evb = time_on_stream(fb, 20, stream)
+        tb = evb / 20
+        result["batch64"] = {
+            "gbs_db": round(bytes_db / tb / 1e9, 2),
+            "queries_per_s": round(B / tb, 1),
+            "served_gbs": round(B * bytes_db / tb / 1e9, 1),
+            "ms_per_batch": round(tb * 1e3, 4),
+            "mfma_frac": round(8.0 * R * C * B / tb / 1e12 / INT8_PEAK_TOPS, 4),
+            "hbm_frac": round(bytes_db / tb / 1e9 / HBM_PEAK_GBS, 4),
+        }
+        log("offline hint, n = 1024")
+        A = workload.device_u32((C, n), workload.SEED_BASE + 4, dev)
+        H = torch.empty((R, n), dtype=torch.int32, device=dev)
+        wsh = db.workspace(n)
+        fh = lambda: db.setup_hint(A, out=H, ws=wsh)
+        fh()
+        wallh, evh = time_on_stream(fh, 3, stream)
+        th = evh / 3
+        result["hint"] = {"ms": round(th * 1e3, 3),
+                          "tops": round(8.0 * R * C * n / th / 1e12, 1),
+                          "mfma_frac": round(8.0 * R * C * n / th / 1e12 / INT8_PEAK_TOPS, 4)}
+        del A, H, Q, out
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ~10 s")
+        result["cpu_baseline"] = cpu_baseline(R, C)
+    db.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

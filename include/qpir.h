@@ -1,0 +1,176 @@
+/*
+ * qpir.h -- C ABI of the MI355X (gfx950) PIR Answer library.
+ *
+ * The library computes the server side of single-server LWE private
+ * information retrieval over a byte database held in GPU memory:
+ *
+ *   answer      a   = D q        mod 2^32   (D: R x C bytes, q: C words)
+ *   batch       Out = D Q        mod 2^32   (Q: C x B words)
+ *   hint        H   = D A        mod 2^32   (A: C x n words, offline)
+ *
+ * This is the response step of the PIR interface (Definition 1: each
+ * database server turns a query into a response derived from its local
+ * database), its multi-request form (the batched responses of Section 5.2,
+ * Algorithms 3 and 4), and the offline/online split of Section 5.3 (the
+ * client-independent product D A is computed ahead of the online phase).
+ * The paper admits any post-quantum PIR in place of its three
+ * instantiations (Section 5.1); this library provides the LWE-based one,
+ * whose response is a plain matrix-vector product modulo 2^32.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Pointers prefixed d_ are DEVICE pointers on the device that was current
+ *   at pir_db_open.  The caller owns every buffer; the library neither frees
+ *   nor retains them after the call returns, except the database bytes that
+ *   a handle borrows (see pir_db_open).
+ * - Matrices are row-major, elements of 32-bit words are unsigned and all
+ *   arithmetic wraps modulo 2^32 (results are exact, bit for bit).
+ * - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
+ *   and the call returns without waiting; results are valid once the stream
+ *   reaches that point.  Only pir_db_open and pir_db_close synchronize.
+ * - Arguments are checked before anything is enqueued.  On any error the
+ *   call returns a status other than PIR_OK and enqueues nothing, so outputs
+ *   are left untouched.  No call prints, aborts or throws.
+ * - Calls that take a workspace (d_ws, ws_bytes) use it as scratch device
+ *   memory of at least pir_workspace_bytes(...) bytes, 256-byte aligned; the
+ *   library allocates no device memory on these paths, so they can be
+ *   captured into a HIP graph.  Concurrent calls must not share a workspace.
+ */
+#ifndef QPIR_H
+#define QPIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pir_status {
+    PIR_OK = 0,
+    PIR_ERR_INVALID_ARG = 1,   /* null pointer, bad handle, zero size */
+    PIR_ERR_SHAPE = 2,         /* sizes that do not fit the handle or limits */
+    PIR_ERR_NO_MEMORY = 3,     /* device or host allocation failed */
+    PIR_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
+    PIR_ERR_UNSUPPORTED = 5,   /* device is not gfx950 */
+    PIR_ERR_WORKSPACE = 6      /* workspace missing, too small or misaligned */
+} pir_status;
+
+/* A hipStream_t, passed as an opaque pointer. */
+typedef void* pir_stream_t;
+
+/* Opaque database handle. */
+typedef struct pir_db pir_db_t;
+
+/* Static description of a status code; never NULL. */
+const char* pir_status_string(pir_status status);
+
+/* Library ABI version, (major << 16) | minor. */
+uint32_t pir_version(void);
+
+/*
+ * Open a handle on a database resident in device memory (the database is
+ * kept in GPU memory for its lifetime, Section 7: no per-query transfers).
+ *
+ *   d_D        R x C bytes; row r starts at d_D + r * row_pitch.  BORROWED:
+ *              the caller keeps the memory alive and unchanged (except
+ *              through pir_update_rows) until pir_db_close.
+ *   rows, cols R >= 1, C >= 1, both < 2^31.
+ *   row_pitch  bytes between row starts, >= cols.  The fast paths need
+ *              d_D and row_pitch to be multiples of 16; other values are
+ *              served by slower, equally exact kernels.
+ *   stream     stream for the metadata pass (per-row byte sums, R words of
+ *              device memory allocated and owned by the handle).  The call
+ *              synchronizes this stream before returning.
+ *   out        receives the handle.
+ *
+ * Errors: PIR_ERR_INVALID_ARG (null d_D or out), PIR_ERR_SHAPE (sizes),
+ * PIR_ERR_UNSUPPORTED (current device is not gfx950), PIR_ERR_NO_MEMORY,
+ * PIR_ERR_DEVICE.
+ */
+pir_status pir_db_open(uint8_t* d_D, uint64_t rows, uint64_t cols, uint64_t row_pitch,
+                       pir_stream_t stream, pir_db_t** out);
+
+/* Release the handle and its metadata.  Synchronizes the device first so no
+ * queued work still reads the metadata.  NULL is accepted (no-op). */
+pir_status pir_db_close(pir_db_t* db);
+
+/* Shape of an open handle. */
+pir_status pir_db_shape(const pir_db_t* db, uint64_t* rows, uint64_t* cols);
+
+/*
+ * Workspace bytes needed by a call on `db`:
+ *   batch == 0   pir_answer
+ *   batch == B   pir_answer_batch with B queries, pir_setup_hint and
+ *                pir_hint_update_rows with n = B.
+ * The value may be 0.
+ */
+size_t pir_workspace_bytes(const pir_db_t* db, uint32_t batch);
+
+/*
+ * Single-query Answer: a[r] = sum_j D[r][j] * q[j] mod 2^32  (Definition 1,
+ * response step; one request of Algorithm 3/4's batch).
+ *
+ *   d_q   C words (the query).  16-byte alignment enables the fast path.
+ *   d_a   R words (the answer).  Must not overlap d_q or the database.
+ *   d_ws  workspace of pir_workspace_bytes(db, 0) bytes (NULL allowed when
+ *         that is 0).
+ */
+pir_status pir_answer(pir_db_t* db, const uint32_t* d_q, uint32_t* d_a,
+                      void* d_ws, size_t ws_bytes, pir_stream_t stream);
+
+/*
+ * Batched Answer: Out[r][b] = sum_j D[r][j] * Q[j][b] mod 2^32 for B
+ * independent queries (the multi-request response of Section 5.2).  Column b
+ * is bit-identical to pir_answer on Q[:, b].  B == 0 is a no-op (PIR_OK).
+ *
+ *   d_Q    C x B words, row-major (query b is column b).
+ *   d_out  R x B words, row-major.
+ *   d_ws   workspace of pir_workspace_bytes(db, B) bytes.
+ */
+pir_status pir_answer_batch(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint32_t* d_out,
+                            void* d_ws, size_t ws_bytes, pir_stream_t stream);
+
+/*
+ * Offline hint: H = D A mod 2^32 (the client-independent part of the
+ * response, moved off the online path as in Section 5.3).
+ *
+ *   d_A   C x n words, row-major (the public LWE matrix).
+ *   d_H   R x n words, row-major.
+ *   d_ws  workspace of pir_workspace_bytes(db, n) bytes.
+ */
+pir_status pir_setup_hint(pir_db_t* db, const uint32_t* d_A, uint32_t n, uint32_t* d_H,
+                          void* d_ws, size_t ws_bytes, pir_stream_t stream);
+
+/*
+ * Database refresh (records are rewritten each validity interval, Section
+ * 4.2): D[rows[i]][:] = new[i][:] for i < m, and the handle's per-row
+ * metadata is updated to match.
+ *
+ *   d_rows  m DISTINCT row indices < R (device).  Indices >= R are skipped;
+ *           duplicate indices leave the affected rows unspecified.
+ *   d_new   m x C bytes, row-major, tightly packed.
+ *   The caller orders this call after every queued answer on the database
+ *   (same stream, or an event) -- it writes the borrowed bytes.
+ */
+pir_status pir_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
+                           const uint8_t* d_new, pir_stream_t stream);
+
+/*
+ * Incremental hint after a refresh: H[rows[i]][:] = D[rows[i]][:] A mod 2^32
+ * for i < m; every other row of H is left as it is.  Equal to a full
+ * pir_setup_hint on the refreshed database, at the cost of m rows.
+ *
+ *   d_rows  as for pir_update_rows.
+ *   d_A     C x n words; d_H R x n words.
+ *   d_ws    workspace of pir_workspace_bytes(db, n) bytes.
+ */
+pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
+                                const uint32_t* d_A, uint32_t n, uint32_t* d_H,
+                                void* d_ws, size_t ws_bytes, pir_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPIR_H */

@@ -1,0 +1,252 @@
+"""ctypes binding of ``libqpir.so`` (argument marshalling only).
+
+Every computation runs in the HIP library.  If the library is missing or
+cannot be loaded, :func:`lib` raises: there is no fallback of any kind.
+Tensors are torch tensors on the GPU; 32-bit words may be ``torch.int32`` or
+``torch.uint32`` (the bits are what count).  Each call enqueues on the
+current torch stream of the tensor's device unless a stream is given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqpir.so")
+
+PIR_OK = 0
+STATUS_NAMES = {
+    0: "PIR_OK", 1: "PIR_ERR_INVALID_ARG", 2: "PIR_ERR_SHAPE", 3: "PIR_ERR_NO_MEMORY",
+    4: "PIR_ERR_DEVICE", 5: "PIR_ERR_UNSUPPORTED", 6: "PIR_ERR_WORKSPACE",
+}
+
+_lib = None
+_lock = threading.Lock()
+
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_U32 = ctypes.c_uint32
+_SZ = ctypes.c_size_t
+_ST = ctypes.c_int
+
+# name -> (restype, argtypes); mirrors include/qpir.h
+SIGNATURES = {
+    "pir_status_string": (ctypes.c_char_p, [_ST]),
+    "pir_version": (_U32, []),
+    "pir_db_open": (_ST, [_P, _U64, _U64, _U64, _P, ctypes.POINTER(_P)]),
+    "pir_db_close": (_ST, [_P]),
+    "pir_db_shape": (_ST, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "pir_workspace_bytes": (_SZ, [_P, _U32]),
+    "pir_answer": (_ST, [_P, _P, _P, _P, _SZ, _P]),
+    "pir_answer_batch": (_ST, [_P, _P, _U32, _P, _P, _SZ, _P]),
+    "pir_setup_hint": (_ST, [_P, _P, _U32, _P, _P, _SZ, _P]),
+    "pir_update_rows": (_ST, [_P, _P, _U32, _P, _P]),
+    "pir_hint_update_rows": (_ST, [_P, _P, _U32, _P, _U32, _P, _P, _SZ, _P]),
+}
+
+
+class PirError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{what}: {name} ({_status_string(status)})")
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libqpir.so``; raise if it is not built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is not built; run `python -m paper_2510_03631_amd.build`")
+            h = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(h, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = h
+    return _lib
+
+
+def _status_string(status: int) -> str:
+    try:
+        return lib().pir_status_string(status).decode()
+    except Exception:
+        return "?"
+
+
+def check(status: int, what: str) -> None:
+    if status != PIR_OK:
+        raise PirError(status, what)
+
+
+def _stream_ptr(stream, device) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return stream.cuda_stream
+
+
+_WORD = (torch.int32, torch.uint32)
+
+
+def _ptr_words(t: torch.Tensor, name: str, shape, device) -> int:
+    if t.dtype not in _WORD:
+        raise TypeError(f"{name}: expected a 32-bit word tensor, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name}: must be a contiguous tensor on {device}")
+    return t.data_ptr()
+
+
+def _ptr_bytes(t: torch.Tensor, name: str, shape, device) -> int:
+    if t.dtype != torch.uint8:
+        raise TypeError(f"{name}: expected uint8, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name}: must be a contiguous tensor on {device}")
+    return t.data_ptr()
+
+
+class Database:
+    """A database resident in GPU memory, opened through ``pir_db_open``.
+
+    ``D`` is an ``R x C`` uint8 CUDA tensor whose rows may be padded (a 2-D
+    view with ``stride(1) == 1``).  The handle borrows its memory; this
+    object keeps a reference so it stays alive until :meth:`close`.
+    """
+
+    def __init__(self, D: torch.Tensor, stream=None):
+        if D.dtype != torch.uint8 or D.dim() != 2 or D.stride(1) != 1 or not D.is_cuda:
+            raise ValueError("D must be a 2-D uint8 CUDA tensor with unit column stride")
+        self.D = D
+        self.device = D.device
+        self.rows, self.cols = int(D.shape[0]), int(D.shape[1])
+        self.pitch = int(D.stride(0)) if self.rows > 1 else self.cols
+        self._ws = {}
+        h = _P()
+        with torch.cuda.device(self.device):
+            check(lib().pir_db_open(D.data_ptr(), self.rows, self.cols, self.pitch,
+                                    _stream_ptr(stream, self.device), ctypes.byref(h)),
+                  "pir_db_open")
+        self._h = h
+
+    # -- lifecycle
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            with torch.cuda.device(self.device):
+                check(lib().pir_db_close(self._h), "pir_db_close")
+            self._h = None
+        self._ws.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise PirError(1, "database is closed")
+        return self._h
+
+    # -- workspace
+    def workspace_bytes(self, batch: int = 0) -> int:
+        return int(lib().pir_workspace_bytes(self.handle, batch))
+
+    def workspace(self, batch: int = 0):
+        """A cached device buffer of ``workspace_bytes(batch)`` bytes (or None)."""
+        nbytes = self.workspace_bytes(batch)
+        if nbytes == 0:
+            return None
+        buf = self._ws.get(batch)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws[batch] = buf
+        return buf
+
+    @staticmethod
+    def _ws_args(ws):
+        if ws is None:
+            return None, 0
+        return ws.data_ptr(), ws.numel() * ws.element_size()
+
+    # -- entry points
+    def answer(self, q: torch.Tensor, out: torch.Tensor = None, stream=None, ws=None):
+        """``a = D q mod 2^32`` (``pir_answer``)."""
+        qp = _ptr_words(q, "q", (self.cols,), self.device)
+        if out is None:
+            out = torch.empty(self.rows, dtype=torch.int32, device=self.device)
+        op = _ptr_words(out, "out", (self.rows,), self.device)
+        if ws is None:
+            ws = self.workspace(0)
+        wp, wn = self._ws_args(ws)
+        check(lib().pir_answer(self.handle, qp, op, wp, wn, _stream_ptr(stream, self.device)),
+              "pir_answer")
+        return out
+
+    def answer_batch(self, Q: torch.Tensor, out: torch.Tensor = None, stream=None, ws=None):
+        """``Out = D Q mod 2^32`` for ``Q`` of shape C x B (``pir_answer_batch``)."""
+        if Q.dim() != 2:
+            raise ValueError("Q must be C x B")
+        B = int(Q.shape[1])
+        qp = _ptr_words(Q, "Q", (self.cols, B), self.device)
+        if out is None:
+            out = torch.empty((self.rows, B), dtype=torch.int32, device=self.device)
+        op = _ptr_words(out, "out", (self.rows, B), self.device)
+        if ws is None:
+            ws = self.workspace(B)
+        wp, wn = self._ws_args(ws)
+        check(lib().pir_answer_batch(self.handle, qp, B, op, wp, wn,
+                                     _stream_ptr(stream, self.device)), "pir_answer_batch")
+        return out
+
+    def setup_hint(self, A: torch.Tensor, out: torch.Tensor = None, stream=None, ws=None):
+        """``H = D A mod 2^32`` for ``A`` of shape C x n (``pir_setup_hint``)."""
+        n = int(A.shape[1])
+        ap = _ptr_words(A, "A", (self.cols, n), self.device)
+        if out is None:
+            out = torch.empty((self.rows, n), dtype=torch.int32, device=self.device)
+        op = _ptr_words(out, "H", (self.rows, n), self.device)
+        if ws is None:
+            ws = self.workspace(n)
+        wp, wn = self._ws_args(ws)
+        check(lib().pir_setup_hint(self.handle, ap, n, op, wp, wn,
+                                   _stream_ptr(stream, self.device)), "pir_setup_hint")
+        return out
+
+    def update_rows(self, rows: torch.Tensor, new: torch.Tensor, stream=None):
+        """``D[rows[i]] = new[i]`` and refresh the handle's metadata."""
+        m = int(rows.numel())
+        rp = _ptr_words(rows, "rows", (m,), self.device)
+        np_ = _ptr_bytes(new, "new", (m, self.cols), self.device)
+        check(lib().pir_update_rows(self.handle, rp, m, np_, _stream_ptr(stream, self.device)),
+              "pir_update_rows")
+
+    def hint_update_rows(self, rows: torch.Tensor, A: torch.Tensor, H: torch.Tensor,
+                         stream=None, ws=None):
+        """``H[rows[i]] = D[rows[i]] A mod 2^32``; other rows of H are kept."""
+        m = int(rows.numel())
+        n = int(A.shape[1])
+        rp = _ptr_words(rows, "rows", (m,), self.device)
+        ap = _ptr_words(A, "A", (self.cols, n), self.device)
+        hp = _ptr_words(H, "H", (self.rows, n), self.device)
+        if ws is None:
+            ws = self.workspace(n)
+        wp, wn = self._ws_args(ws)
+        check(lib().pir_hint_update_rows(self.handle, rp, m, ap, n, hp, wp, wn,
+                                         _stream_ptr(stream, self.device)),
+              "pir_hint_update_rows")
+        return H

@@ -1,0 +1,246 @@
+// Single-query Answer: a[r] = sum_j D[r][j] * q[j] mod 2^32.
+//
+// The server's per-query response (Definition 1) is a matrix-vector product
+// whose cost is streaming the database once: every byte of D is used once,
+// so the kernel is bound by HBM bandwidth (the paper makes the same
+// observation for its XOR variant in Section 5.2: low operational intensity,
+// coalescing rather than matrix units).  Design for gfx950:
+//
+// * q is split into four byte limbs, q = sum_k 2^(8k) q_k, so that
+//   a = sum_k 2^(8k) (D q_k).  Each D q_k is a sum of byte x byte products,
+//   one v_dot4_u32_u8 per four database bytes and limb: 4 VALU ops per
+//   16 database bytes per limb, ~1 op per byte overall, far under the
+//   ~4.9 lane-ops per byte the CUs can spend at full HBM rate.  The dot
+//   instruction wraps modulo 2^32, which is all the answer needs.
+// * A workgroup (4 waves) stages a slice of kSlice query words in LDS as the
+//   four limb planes (split once per workgroup, not per wave).
+// * Each wave owns RW database rows.  One wave-wide 16-byte load covers 1024
+//   contiguous bytes of a row (fully coalesced); the RW row loads of a chunk
+//   are issued back to back so RW KiB per wave are in flight.  The stream is
+//   read with non-temporal loads.
+// * After the column loop each lane holds RW partial sums; they are
+//   transposed through LDS and finished with lane shuffles, so one lane per
+//   row writes the result.
+// * Shapes with too few row blocks to fill the chip split the columns; the
+//   per-split partial sums go to the workspace and a second kernel adds
+//   them (integer addition modulo 2^32 is exact in any order).
+#include "qpir_internal.h"
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kChunk = 1024;   // columns covered by one wave-wide 16-byte load
+constexpr int kSlice = 4096;   // query words staged in LDS at a time
+constexpr int kRW = 16;        // rows per wave
+constexpr int kRowsPerBlock = kRW * kWaves;
+
+// Four consecutive query words -> the four limb words; limb k holds byte k
+// of each word, the first word in the low byte.
+__device__ inline void limbs_of4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                 uint32_t out[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int sh = 8 * k;
+        out[k] = ((x0 >> sh) & 0xFFu) | (((x1 >> sh) & 0xFFu) << 8) |
+                 (((x2 >> sh) & 0xFFu) << 16) | (((x3 >> sh) & 0xFFu) << 24);
+    }
+}
+
+// 16 bytes of a row starting at column c, zero past column `end`.
+template <bool VEC>
+__device__ inline u32x4 load16(const uint8_t* row, uint32_t c, uint32_t end) {
+    if (VEC && c + 16 <= end) {
+        return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row + c));
+    }
+    uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const uint32_t b = (c + e < end) ? row[c + e] : 0u;
+        w[e >> 2] |= b << (8 * (e & 3));
+    }
+    return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+template <int RW, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_answer1(const uint8_t* __restrict__ D, uint64_t pitch,
+                                                      uint32_t R, uint32_t C,
+                                                      const uint32_t* __restrict__ q,
+                                                      uint32_t* __restrict__ out,
+                                                      uint32_t cols_per_split) {
+    __shared__ u32x4 s_limb[4][kSlice / 16];
+    __shared__ uint32_t s_red[kWaves][RW][65];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const uint32_t row0 = (blockIdx.x * kWaves + wave) * RW;
+    const uint32_t cb = blockIdx.y * cols_per_split;
+    const uint32_t ce = min(C, cb + cols_per_split);
+
+    // Rows past the end re-read the last row; their sums are never stored.
+    const uint8_t* rp[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const uint32_t r = min(row0 + (uint32_t)i, R - 1);
+        rp[i] = D + (uint64_t)r * pitch;
+    }
+
+    uint32_t acc[RW][4];
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[i][k] = 0;
+
+    for (uint32_t s0 = cb; s0 < ce; s0 += kSlice) {
+        const uint32_t se = min(ce, s0 + (uint32_t)kSlice);
+        __syncthreads();   // previous slice fully consumed
+        for (int t = tid; t < kSlice / 16; t += kThreads) {
+            const uint32_t c = s0 + 16u * t;
+            uint32_t x[16];
+            if (VEC && c + 16 <= se) {
+                const u32x4* qp = reinterpret_cast<const u32x4*>(q + c);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const u32x4 w = qp[v];
+                    x[4 * v + 0] = w.x;
+                    x[4 * v + 1] = w.y;
+                    x[4 * v + 2] = w.z;
+                    x[4 * v + 3] = w.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) x[e] = (c + e < se) ? q[c + e] : 0u;
+            }
+            uint32_t l[4][4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                uint32_t o[4];
+                limbs_of4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3], o);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) l[k][w] = o[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_limb[k][t] = u32x4{l[k][0], l[k][1], l[k][2], l[k][3]};
+        }
+        __syncthreads();
+
+        for (uint32_t c0 = s0; c0 < se; c0 += kChunk) {
+            const uint32_t li = (c0 - s0) / 16 + lane;
+            u32x4 L[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L[k] = s_limb[k][li];
+            const uint32_t c = c0 + 16u * lane;
+            if (VEC && c0 + kChunk <= se) {
+                u32x4 d[RW];
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+                    d[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rp[i] + c));
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        uint32_t a = acc[i][k];
+                        a = __builtin_amdgcn_udot4(d[i].x, L[k].x, a, false);
+                        a = __builtin_amdgcn_udot4(d[i].y, L[k].y, a, false);
+                        a = __builtin_amdgcn_udot4(d[i].z, L[k].z, a, false);
+                        a = __builtin_amdgcn_udot4(d[i].w, L[k].w, a, false);
+                        acc[i][k] = a;
+                    }
+            } else if (c < se) {
+#pragma unroll
+                for (int i = 0; i < RW; ++i) {
+                    const u32x4 d = load16<VEC>(rp[i], c, se);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        uint32_t a = acc[i][k];
+                        a = __builtin_amdgcn_udot4(d.x, L[k].x, a, false);
+                        a = __builtin_amdgcn_udot4(d.y, L[k].y, a, false);
+                        a = __builtin_amdgcn_udot4(d.z, L[k].z, a, false);
+                        a = __builtin_amdgcn_udot4(d.w, L[k].w, a, false);
+                        acc[i][k] = a;
+                    }
+                }
+            }
+        }
+    }
+
+    // a_i = sum_k 2^(8k) acc[i][k]; then sum the 64 lanes of each row.
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const uint32_t v = acc[i][0] + (acc[i][1] << 8) + (acc[i][2] << 16) + (acc[i][3] << 24);
+        s_red[wave][i][lane] = v;
+    }
+    __syncthreads();
+    constexpr int kLanesPerRow = 64 / RW;
+    const int i = lane / kLanesPerRow;
+    const int part = lane % kLanesPerRow;
+    uint32_t v = 0;
+#pragma unroll
+    for (int t = 0; t < RW; ++t) v += s_red[wave][i][part * RW + t];
+#pragma unroll
+    for (int off = 1; off < kLanesPerRow; off <<= 1) v += __shfl_xor(v, off);
+    const uint32_t r = row0 + (uint32_t)i;
+    if (part == 0 && r < R) out[(uint64_t)blockIdx.y * R + r] = v;
+}
+
+__global__ void k_sum_splits(const uint32_t* __restrict__ part, uint32_t R, uint32_t S,
+                             uint32_t* __restrict__ out) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    uint32_t v = 0;
+    for (uint32_t s = 0; s < S; ++s) v += part[(uint64_t)s * R + r];
+    out[r] = v;
+}
+
+struct SplitPlan {
+    uint32_t splits;
+    uint32_t cols_per_split;
+};
+
+// Split the columns only when the row blocks alone cannot give every CU
+// a workgroup.
+SplitPlan plan_splits(const pir_db_t* db) {
+    const uint64_t blocks = (db->rows + kRowsPerBlock - 1) / kRowsPerBlock;
+    const uint64_t chunks = (db->cols + kChunk - 1) / kChunk;
+    uint64_t s = 1;
+    if (blocks < 256) s = (512 + blocks - 1) / blocks;
+    if (s > chunks) s = chunks;
+    if (s < 1) s = 1;
+    uint64_t cps = ((db->cols + s - 1) / s + kChunk - 1) / kChunk * kChunk;
+    s = (db->cols + cps - 1) / cps;
+    return SplitPlan{(uint32_t)s, (uint32_t)cps};
+}
+
+}  // namespace
+
+size_t gemv_workspace_bytes(const pir_db_t* db) {
+    const SplitPlan p = plan_splits(db);
+    return p.splits > 1 ? round_up((size_t)p.splits * db->rows * 4, kWsAlign) : 0;
+}
+
+pir_status gemv_answer(const pir_db_t* db, const uint32_t* q, uint32_t* a, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
+    const SplitPlan p = plan_splits(db);
+    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
+    uint32_t* dst = a;
+    if (p.splits > 1) {
+        if (!ws || ws_bytes < gemv_workspace_bytes(db) || ((uintptr_t)ws % kWsAlign))
+            return PIR_ERR_WORKSPACE;
+        dst = static_cast<uint32_t*>(ws);
+    }
+    const bool vec = db->aligned && ((uintptr_t)q % 16 == 0);
+    dim3 grid((R + kRowsPerBlock - 1) / kRowsPerBlock, p.splits);
+    if (vec)
+        k_answer1<kRW, true><<<grid, kThreads, 0, s>>>(db->D, db->pitch, R, C, q, dst,
+                                                       p.cols_per_split);
+    else
+        k_answer1<kRW, false><<<grid, kThreads, 0, s>>>(db->D, db->pitch, R, C, q, dst,
+                                                        p.cols_per_split);
+    PIR_LAUNCH_CHECK();
+    if (p.splits > 1) {
+        k_sum_splits<<<(R + 255) / 256, 256, 0, s>>>(dst, R, p.splits, a);
+        PIR_LAUNCH_CHECK();
+    }
+    return PIR_OK;
+}

@@ -1,0 +1,343 @@
+// Batched Answer and offline hint on the int8 matrix cores.
+//
+//   Out[r][b] = sum_j D[r][j] * Q[j][b]  mod 2^32
+//
+// (the multi-request response of Section 5.2, Algorithm 4's batched product,
+// here over Z/2^32; the hint H = D A is the same product with A in place of
+// Q, Section 5.3's offline work).
+//
+// gfx950 has only signed int8 matrix instructions, so both operands are
+// centred.  With q = sum_k 2^(8k) q_k (byte limbs), q_k = q'_k + 128 and
+// D = D' + 128 (D' = D xor 0x80 read as int8, likewise q'_k):
+//
+//   D q = sum_k 2^(8k) (D' q'_k)  +  128 sum_k 2^(8k) colsum(q'_k)
+//                                 +  0x80808080 rowsum(D)
+//
+// and sum_k 2^(8k) colsum(q'_k) = colsum(q) - C * 0x80808080.  So one int8
+// GEMM with M = R, K = C and N = 4 * B (the four limb planes of every query
+// side by side) gives the products P_k = D' q'_k; the epilogue adds
+// P_0 + 2^8 P_1 + 2^16 P_2 + 2^24 P_3, the per-query column term and the
+// per-row term kept in the database handle.  Every step is exact modulo
+// 2^32: the int32 accumulators of the matrix instruction wrap modulo 2^32
+// (two's complement), and only the residue is ever used.
+//
+// Kernels
+//   k_zero_words  clear the column sums
+//   k_ingest      Q (C x B words) -> QL (N x Cp centred int8, K-contiguous),
+//                 colsum[b] += sum_j Q[j][b]
+//   k_gemm        int8 MFMA 32x32x32 tiles, LDS double staging through
+//                 registers, fused epilogue, optional row gather/scatter
+//                 (the incremental hint touches only refreshed rows).
+//
+// QL row index of (query b, limb k): n = (b / 32) * 128 + k * 32 + (b % 32),
+// so the four limbs of a query land in the same lane of four adjacent 32x32
+// output tiles and the epilogue combines them in registers.
+#include "qpir_internal.h"
+
+namespace {
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+constexpr uint32_t kCentreWord = 0x80808080u;
+constexpr int kKPad = 256;      // QL rows are padded with zeros to a multiple of this
+
+__global__ void k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Block: 64 query coordinates j x 32 queries b.  Reads Q coalesced along b,
+// transposes through LDS, writes 4 limb rows x 64 bytes per query.
+__global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, uint32_t C,
+                                                uint32_t B, uint32_t Cp,
+                                                int8_t* __restrict__ QL,
+                                                uint32_t* __restrict__ colsum) {
+    __shared__ uint32_t s[32][65];
+    const int t = threadIdx.x;
+    const uint32_t j0 = blockIdx.x * 64u;
+    const uint32_t b0 = blockIdx.y * 32u;
+    {
+        const int bb = t & 31;
+        const uint32_t b = b0 + bb;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int jj = (t >> 5) + 8 * p;
+            const uint32_t j = j0 + jj;
+            s[bb][jj] = (j < C && b < B) ? Q[(uint64_t)j * B + b] : 0u;
+        }
+    }
+    __syncthreads();
+    const int limb = t >> 6;
+    const int bb = (t >> 1) & 31;
+    const int half = t & 1;
+    const uint32_t b = b0 + bb;
+    uint32_t w[8];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int jj = 32 * half + 4 * e + x;
+            const uint32_t j = j0 + jj;
+            const uint32_t v = s[bb][jj];
+            sum += v;
+            const uint32_t byte = (j < C && b < B) ? (((v >> (8 * limb)) & 0xFFu) ^ 0x80u) : 0u;
+            word |= byte << (8 * x);
+        }
+        w[e] = word;
+    }
+    const uint32_t n = (b0 / 32u) * 128u + (uint32_t)limb * 32u + (uint32_t)bb;
+    u32x4* dst = reinterpret_cast<u32x4*>(QL + (uint64_t)n * Cp + j0 + 32u * half);
+    dst[0] = u32x4{w[0], w[1], w[2], w[3]};
+    dst[1] = u32x4{w[4], w[5], w[6], w[7]};
+    if (limb == 0) {
+        sum += __shfl_xor(sum, 1);
+        if (half == 0 && b < B) atomicAdd(&colsum[b], sum);
+    }
+}
+
+// ---------------------------------------------------------------- GEMM
+template <int WM_, int WN_, int TM_, int TN_, int BK_>
+struct Tile {
+    static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, BK = BK_;
+    static constexpr int BM = WM * TM * 32;
+    static constexpr int BN = WN * TN * 32;
+    static constexpr int LDK = BK + 16;              // padded LDS row, bytes
+    static constexpr int A_LOADS = BM * BK / (256 * 16);
+    static constexpr int B_LOADS = BN * BK / (256 * 16);
+    static constexpr int SEGS = BK / 16;             // 16-byte pieces per row
+    static_assert(WM * WN == 4, "four waves");
+    static_assert(TN % 4 == 0, "a wave covers whole groups of four limbs");
+    static_assert(A_LOADS >= 1 && B_LOADS >= 1, "tile too small for 256 threads");
+};
+
+template <bool VEC>
+__device__ inline u32x4 load_row16(const uint8_t* row, uint32_t k, uint32_t C) {
+    if (VEC && k + 16 <= C) return *reinterpret_cast<const u32x4*>(row + k);
+    uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const uint32_t b = (k + e < C) ? row[k + e] : 0u;
+        w[e >> 2] |= b << (8 * (e & 3));
+    }
+    return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+// Block tile BM x BN of Out; 4 waves in a WM x WN grid, each computing
+// (TM*32) x (TN*32) with 32x32x32 int8 MFMAs.
+template <class T, bool VEC, bool GATHER>
+__global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uint64_t pitch,
+                                              uint32_t R, uint32_t C,
+                                              const uint32_t* __restrict__ rows, uint32_t M,
+                                              const int8_t* __restrict__ QL, uint32_t Cp,
+                                              uint32_t B, uint32_t n_tiles,
+                                              const uint32_t* __restrict__ colsum,
+                                              const uint32_t* __restrict__ rowterm,
+                                              uint32_t* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) uint8_t sA[T::BM * T::LDK];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[T::BN * T::LDK];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / T::WN;
+    const int wn = wave % T::WN;
+
+    // Tiles are numbered n-fastest.  Consecutive workgroups are dealt to
+    // the 8 XCDs in turn; remap so each XCD works on a contiguous range of
+    // tiles (the row blocks of D it reads stay in its own L2).
+    const uint32_t nblk = gridDim.x;
+    uint32_t bid = blockIdx.x;
+    {
+        const uint32_t per = nblk / 8u;
+        const uint32_t x = bid % 8u, l = bid / 8u;
+        if (bid < per * 8u) bid = x * per + l;
+    }
+    const uint32_t tile_m = bid / n_tiles;
+    const uint32_t tile_n = bid % n_tiles;
+    const uint32_t m0 = tile_m * T::BM;
+    const uint32_t n0 = tile_n * T::BN;
+
+    // Global load assignment: thread -> (row, 16-byte segment).
+    const int seg = tid % T::SEGS;
+    const int rsub = tid / T::SEGS;
+    constexpr int ROWS_PER_PASS = 256 / T::SEGS;
+
+    const uint8_t* arow[T::A_LOADS];
+#pragma unroll
+    for (int p = 0; p < T::A_LOADS; ++p) {
+        uint32_t i = m0 + rsub + p * ROWS_PER_PASS;
+        i = i < M ? i : M - 1;
+        const uint32_t r = GATHER ? rows[i] : i;
+        arow[p] = D + (uint64_t)(r < R ? r : R - 1) * pitch;
+    }
+    const int8_t* brow[T::B_LOADS];
+#pragma unroll
+    for (int p = 0; p < T::B_LOADS; ++p)
+        brow[p] = QL + (uint64_t)(n0 + rsub + p * ROWS_PER_PASS) * Cp;
+
+    u32x4 ra[T::A_LOADS], rb[T::B_LOADS];
+    auto gload = [&](uint32_t k0) {
+        const uint32_t k = k0 + 16u * seg;
+#pragma unroll
+        for (int p = 0; p < T::A_LOADS; ++p) ra[p] = load_row16<VEC>(arow[p], k, C);
+#pragma unroll
+        for (int p = 0; p < T::B_LOADS; ++p)
+            rb[p] = *reinterpret_cast<const u32x4*>(brow[p] + k);
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int p = 0; p < T::A_LOADS; ++p) {
+            const u32x4 v = ra[p] ^ u32x4{kCentreWord, kCentreWord, kCentreWord, kCentreWord};
+            *reinterpret_cast<u32x4*>(&sA[(rsub + p * ROWS_PER_PASS) * T::LDK + 16 * seg]) = v;
+        }
+#pragma unroll
+        for (int p = 0; p < T::B_LOADS; ++p)
+            *reinterpret_cast<u32x4*>(&sB[(rsub + p * ROWS_PER_PASS) * T::LDK + 16 * seg]) = rb[p];
+    };
+
+    i32x16 acc[T::TM][T::TN];
+#pragma unroll
+    for (int a = 0; a < T::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < T::TN; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
+
+    const int frag_row = lane & 31;
+    const int frag_k = 16 * (lane >> 5);
+
+    gload(0);
+    lstore();
+    __syncthreads();
+    for (uint32_t k0 = 0; k0 < C; k0 += T::BK) {
+        const bool more = k0 + T::BK < C;
+        if (more) gload(k0 + T::BK);
+#pragma unroll
+        for (int ks = 0; ks < T::BK / 32; ++ks) {
+            i32x4 fa[T::TM], fb[T::TN];
+#pragma unroll
+            for (int a = 0; a < T::TM; ++a)
+                fa[a] = *reinterpret_cast<const i32x4*>(
+                    &sA[(wm * T::TM * 32 + a * 32 + frag_row) * T::LDK + ks * 32 + frag_k]);
+#pragma unroll
+            for (int b = 0; b < T::TN; ++b)
+                fb[b] = *reinterpret_cast<const i32x4*>(
+                    &sB[(wn * T::TN * 32 + b * 32 + frag_row) * T::LDK + ks * 32 + frag_k]);
+#pragma unroll
+            for (int a = 0; a < T::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < T::TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+        if (more) {
+            lstore();
+            __syncthreads();
+        }
+    }
+
+    // Epilogue: combine limbs, add the centring terms, store.
+    const uint32_t cterm_base = (uint32_t)C * kCentreWord;
+#pragma unroll
+    for (int g = 0; g < T::TN / 4; ++g) {
+        const uint32_t bq = (n0 + wn * T::TN * 32) / 4u + 32u * g + (uint32_t)(lane & 31);
+        const uint32_t colterm = 128u * (bq < B ? colsum[bq] - cterm_base : 0u);
+#pragma unroll
+        for (int a = 0; a < T::TM; ++a) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const uint32_t i = m0 + wm * T::TM * 32 + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+                if (i < M && bq < B) {
+                    const uint32_t r = GATHER ? rows[i] : i;
+                    if (r < R) {
+                        const uint32_t p0 = (uint32_t)acc[a][4 * g + 0][v];
+                        const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
+                        const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
+                        const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
+                        out[(uint64_t)r * B + bq] =
+                            p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Tile shapes: small batches (one group of 32 queries) use 4 waves along M;
+// larger ones a 2 x 2 wave grid of 64 x 128 wave tiles.
+using TileNarrow = Tile<4, 1, 1, 4, 128>;   // 128 x 128
+using TileWide = Tile<2, 2, 2, 4, 128>;     // 128 x 256
+
+template <class T>
+pir_status launch_gemm(const pir_db_t* db, const uint32_t* rows, uint32_t M, const int8_t* QL,
+                       uint32_t Cp, uint32_t B, uint32_t N, const uint32_t* colsum,
+                       uint32_t* out, hipStream_t s) {
+    const uint32_t n_tiles = (N + T::BN - 1) / T::BN;
+    const uint32_t m_tiles = (M + T::BM - 1) / T::BM;
+    const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
+#define PIR_GEMM(VEC, GATHER)                                                              \
+    k_gemm<T, VEC, GATHER><<<(uint32_t)blocks, 256, 0, s>>>(db->D, db->pitch, R, C, rows, M, \
+                                                             QL, Cp, B, n_tiles, colsum,      \
+                                                             db->rowterm, out)
+    if (db->aligned) {
+        if (rows) PIR_GEMM(true, true); else PIR_GEMM(true, false);
+    } else {
+        if (rows) PIR_GEMM(false, true); else PIR_GEMM(false, false);
+    }
+#undef PIR_GEMM
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
+struct BatchLayout {
+    uint32_t Bp, N, Cp;
+    size_t ql_bytes, colsum_off, total;
+};
+
+BatchLayout batch_layout(const pir_db_t* db, uint32_t B) {
+    BatchLayout L;
+    // One group of 32 queries uses the 128-wide tile; larger batches are
+    // padded to whole 256-wide tiles (64 queries).  Padded queries are zero.
+    L.Bp = B <= 32u ? 32u : (B + 63u) / 64u * 64u;
+    L.N = 4u * L.Bp;
+    L.Cp = (uint32_t)round_up(db->cols, kKPad);
+    L.ql_bytes = round_up((size_t)L.N * L.Cp, kWsAlign);
+    L.colsum_off = L.ql_bytes;
+    L.total = L.colsum_off + round_up((size_t)L.Bp * 4, kWsAlign);
+    return L;
+}
+
+}  // namespace
+
+size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B) {
+    if (B == 0) return 0;
+    return batch_layout(db, B).total;
+}
+
+pir_status mfma_answer_batch(const pir_db_t* db, const uint32_t* Q, uint32_t B, uint32_t* out,
+                             const uint32_t* rows, uint32_t m, void* ws, size_t ws_bytes,
+                             hipStream_t s) {
+    const BatchLayout L = batch_layout(db, B);
+    if (!ws || ws_bytes < L.total || ((uintptr_t)ws % kWsAlign)) return PIR_ERR_WORKSPACE;
+    uint8_t* base = static_cast<uint8_t*>(ws);
+    int8_t* QL = reinterpret_cast<int8_t*>(base);
+    uint32_t* colsum = reinterpret_cast<uint32_t*>(base + L.colsum_off);
+    const uint32_t C = (uint32_t)db->cols;
+
+    k_zero_words<<<(L.Bp + 255) / 256, 256, 0, s>>>(colsum, L.Bp);
+    PIR_LAUNCH_CHECK();
+    dim3 ig(L.Cp / 64, L.Bp / 32);
+    k_ingest<<<ig, 256, 0, s>>>(Q, C, B, L.Cp, QL, colsum);
+    PIR_LAUNCH_CHECK();
+
+    const uint32_t M = rows ? m : (uint32_t)db->rows;
+    if (M == 0) return PIR_OK;
+    if (L.N <= 128)
+        return launch_gemm<TileNarrow>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
+    return launch_gemm<TileWide>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
+}
