@@ -32,26 +32,24 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2510_03631_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + f.read())
-    return h.hexdigest()[:16]
+def source_hash(filename: str) -> str:
+    """Hash of the kernel source file a traffic record was measured on."""
+    path = os.path.join(ROOT, "paper_2510_03631_amd", "csrc", filename)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def load_traffic(kernel: str):
-    """HBM bytes per launch measured with rocprofv3 counters, if they were
-    taken on the current kernel sources (else None)."""
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy's readings), if they were taken on the
+    current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f).get(kernel)
-    except (OSError, ValueError):
-        return None
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+        if not rec or rec.get("source_hash") != source_hash(rec["source_file"]):
+            return None
+    except (OSError, ValueError, KeyError):
         return None
     return rec.get("bytes_per_launch")
 
@@ -97,6 +95,55 @@ def cpu_baseline(R: int, C: int, seconds: float = 10.0):
                       f"{n} passes in {el:.1f} s (plain C loops, OpenMP)"}
 
 
+def profile_mode(args, dev, stream) -> int:
+    """One kernel family on the headline database, for counter runs.
+
+    ``calibrate`` times plain device copies of 1 GiB (the blit kernel behind
+    a device-to-device copy, and an elementwise negate), whose HBM bytes are
+    known exactly; they scale the FETCH_SIZE / WRITE_SIZE counters.
+    """
+    import torch
+    import paper_2510_03631_amd as qp
+    import workload
+    shape = workload.CONFIGS["spectrum_1q"]
+    R, C, n = shape.rows, shape.cols, shape.n
+    if args.profile == "calibrate":
+        x = workload.device_u32((1 << 28,), workload.SEED_BASE + 9, dev)
+        y = torch.empty_like(x)
+        for _ in range(args.warmup + args.steps):
+            y.copy_(x)
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "calibrate", "bytes_read": x.numel() * 4,
+                          "bytes_written": x.numel() * 4, "steps": args.steps}))
+        return 0
+    D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
+    db = qp.Database(D)
+    if args.profile == "answer":
+        q = workload.device_u32((C,), workload.SEED_BASE + 2, dev)
+        a = torch.empty(R, dtype=torch.int32, device=dev)
+        ws = db.workspace(0)
+        fn = lambda: db.answer(q, out=a, ws=ws)
+    elif args.profile == "batch":
+        B = 64
+        Q = workload.device_u32((C, B), workload.SEED_BASE + 3, dev)
+        out = torch.empty((R, B), dtype=torch.int32, device=dev)
+        ws = db.workspace(B)
+        fn = lambda: db.answer_batch(Q, out=out, ws=ws)
+    else:
+        A = workload.device_u32((C, n), workload.SEED_BASE + 4, dev)
+        H = torch.empty((R, n), dtype=torch.int32, device=dev)
+        ws = db.workspace(n)
+        fn = lambda: db.setup_hint(A, out=H, ws=ws)
+    for _ in range(args.warmup):
+        fn()
+    wall, ev = time_on_stream(fn, args.steps, stream)
+    print(json.dumps({"profile": args.profile, "steps": args.steps,
+                      "avg_us": round(ev / args.steps * 1e6, 2)}))
+    db.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +151,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--profile", choices=["answer", "batch", "hint", "calibrate"],
+                    help="run only one kernel family (for rocprofv3 runs) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -119,6 +168,8 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.profile:
+        return profile_mode(args, dev, stream)
     shape = workload.CONFIGS["spectrum_1q"]
     R, C, n = shape.rows, shape.cols, shape.n
 
