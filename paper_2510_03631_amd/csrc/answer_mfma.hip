@@ -266,6 +266,242 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
     }
 }
 
+// ---------------------------------------------------------------- GEMM, LDS ring
+// The main kernel for aligned databases with C a multiple of 16.  Global
+// tiles go straight to LDS with global_load_lds_dwordx4 (no register
+// staging), into a ring of STAGES k-tiles of 64 bytes, so STAGES-1 tiles are
+// in flight while one is consumed.  A 64-byte LDS row holds four 16-byte
+// slots; slot = segment ^ ((row >> 1) & 3) keeps the fragment reads
+// (one row per lane, same segment) free of bank conflicts.  Centring of D
+// (xor 0x80) is applied to the A fragments in registers.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+template <int WM_, int WN_, int TM_, int TN_, int STAGES_>
+struct Ring {
+    static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, STAGES = STAGES_;
+    static constexpr int BK = 64;
+    static constexpr int BM = WM * TM * 32;
+    static constexpr int BN = WN * TN * 32;
+    static constexpr int A_BYTES = BM * BK;
+    static constexpr int STAGE_BYTES = (BM + BN) * BK;
+    static constexpr int A_BLOCKS = BM / 16;             // 1 KiB blocks of 16 rows
+    static constexpr int BLOCKS = (BM + BN) / 16;
+    static constexpr int LOADS = BLOCKS / 4;             // per wave per tile
+    static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
+    static_assert(WM * WN == 4, "four waves");
+    static_assert(TN % 4 == 0, "a wave covers whole groups of four limbs");
+    static_assert(BLOCKS % 4 == 0 && A_BLOCKS % 4 == 0, "blocks split evenly over waves");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+__device__ inline int slot_of(int row, int seg) { return seg ^ ((row >> 1) & 3); }
+
+// s_waitcnt with only vmcnt constrained (gfx9 encoding: vmcnt low bits
+// [3:0], high bits [15:14]; expcnt and lgkmcnt left at their maximum).
+template <int N>
+__device__ inline void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Workgroup barrier without the memory fence of __syncthreads(): the fence
+// would drain every outstanding load (vmcnt(0)) and empty the ring.  Each
+// wave has already waited for its own tile loads (wait_vmcnt), and LDS
+// reads are not moved across the asm statements.
+__device__ inline void ring_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <class T, bool GATHER>
+__global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D, uint64_t pitch,
+                                                   uint32_t R, uint32_t C,
+                                                   const uint32_t* __restrict__ rows, uint32_t M,
+                                                   const int8_t* __restrict__ QL, uint32_t Cp,
+                                                   uint32_t B, uint32_t n_tiles, uint32_t m_tiles,
+                                                   const uint32_t* __restrict__ colsum,
+                                                   const uint32_t* __restrict__ rowterm,
+                                                   uint32_t* __restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / T::WN;
+    const int wn = wave % T::WN;
+
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous range of tile indices, then order tiles in groups of 8 row
+    // tiles so the ~32 workgroups an XCD runs at once share D and QL tiles
+    // in its L2.
+    uint32_t bid = blockIdx.x;
+    {
+        const uint32_t per = gridDim.x / 8u;
+        if (bid < per * 8u) bid = (bid % 8u) * per + bid / 8u;
+    }
+    constexpr uint32_t kGroup = 8;
+    const uint32_t group = bid / (kGroup * n_tiles);
+    const uint32_t first_m = group * kGroup;
+    const uint32_t gsize = min(m_tiles - first_m, kGroup);
+    const uint32_t in_group = bid % (kGroup * n_tiles);
+    const uint32_t tile_m = first_m + in_group % gsize;
+    const uint32_t tile_n = in_group / gsize;
+    const uint32_t m0 = tile_m * T::BM;
+    const uint32_t n0 = tile_n * T::BN;
+
+    // Per-lane source of each of this wave's LOADS block loads.
+    const int lrow = lane >> 2;                           // row within a 1 KiB block
+    const uint8_t* src[T::LOADS];
+    uint32_t seg_off[T::LOADS];
+    bool is_a[T::LOADS];
+#pragma unroll
+    for (int i = 0; i < T::LOADS; ++i) {
+        const int kb = wave + 4 * i;
+        const bool a = kb < T::A_BLOCKS;
+        const int r = (a ? kb : kb - T::A_BLOCKS) * 16 + lrow;
+        const int seg = (lane & 3) ^ ((r >> 1) & 3);
+        is_a[i] = a;
+        seg_off[i] = 16u * seg;
+        if (a) {
+            uint32_t mi = m0 + r;
+            mi = mi < M ? mi : M - 1;
+            uint32_t dr = GATHER ? rows[mi] : mi;
+            dr = dr < R ? dr : R - 1;
+            src[i] = D + (uint64_t)dr * pitch + seg_off[i];
+        } else {
+            src[i] = reinterpret_cast<const uint8_t*>(QL) + (uint64_t)(n0 + r) * Cp + seg_off[i];
+        }
+    }
+    const uint32_t ktiles = (C + T::BK - 1) / T::BK;
+
+    auto issue = [&](uint32_t t) {
+        const uint32_t k0 = t * T::BK;
+        uint8_t* stage = smem + (t % T::STAGES) * T::STAGE_BYTES;
+#pragma unroll
+        for (int i = 0; i < T::LOADS; ++i) {
+            const int kb = wave + 4 * i;
+            uint8_t* dst = stage + kb * 1024;   // A blocks first, then B blocks
+            // D segments past the last column are skipped (their LDS slots
+            // keep old bytes, which meet zero query bytes); QL rows are
+            // zero-padded to Cp and always loaded.
+            if (!is_a[i] || k0 + seg_off[i] + 16 <= C)
+                __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + k0), (lds_void_t*)dst,
+                                                 16, 0, 0);
+        }
+    };
+
+    i32x16 acc[T::TM][T::TN];
+#pragma unroll
+    for (int a = 0; a < T::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < T::TN; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
+
+    const int frow = lane & 31;
+    const int fseg = lane >> 5;
+    const u32x4 centre = u32x4{kCentreWord, kCentreWord, kCentreWord, kCentreWord};
+
+#pragma unroll
+    for (int p = 0; p < T::STAGES - 1; ++p)
+        if ((uint32_t)p < ktiles) issue(p);
+
+    for (uint32_t t = 0; t < ktiles; ++t) {
+        // Tiles t+1 .. t+STAGES-2 were issued after tile t.  While none of
+        // them is the last tile (whose D loads past column C may be skipped
+        // by a whole wave, issuing fewer loads), tile t has landed once at
+        // most (STAGES-2) * LOADS of this wave's loads are outstanding
+        // (loads complete in order).  Otherwise wait for all.  The barrier
+        // then makes every wave's part visible and frees the stage consumed
+        // in the previous iteration.
+        if (t + T::STAGES - 1 < ktiles) wait_vmcnt<(T::STAGES - 2) * T::LOADS>();
+        else wait_vmcnt<0>();
+        ring_barrier();
+        if (t + T::STAGES - 1 < ktiles) issue(t + T::STAGES - 1);
+
+        const uint8_t* sa = smem + (t % T::STAGES) * T::STAGE_BYTES;
+        const uint8_t* sb = sa + T::A_BYTES;
+#pragma unroll
+        for (int ks = 0; ks < T::BK / 32; ++ks) {
+            const int seg = 2 * ks + fseg;
+            i32x4 fa[T::TM], fb[T::TN];
+#pragma unroll
+            for (int a = 0; a < T::TM; ++a) {
+                const int r = wm * T::TM * 32 + a * 32 + frow;
+                u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * slot_of(r, seg));
+                v ^= centre;
+                fa[a] = __builtin_bit_cast(i32x4, v);
+            }
+#pragma unroll
+            for (int b = 0; b < T::TN; ++b) {
+                const int r = wn * T::TN * 32 + b * 32 + frow;
+                fb[b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * slot_of(r, seg));
+            }
+#pragma unroll
+            for (int a = 0; a < T::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < T::TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+    }
+
+    const uint32_t cterm_base = C * kCentreWord;
+#pragma unroll
+    for (int g = 0; g < T::TN / 4; ++g) {
+        const uint32_t bq = (n0 + wn * T::TN * 32) / 4u + 32u * g + (uint32_t)(lane & 31);
+        const uint32_t colterm = 128u * (bq < B ? colsum[bq] - cterm_base : 0u);
+#pragma unroll
+        for (int a = 0; a < T::TM; ++a) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const uint32_t i = m0 + wm * T::TM * 32 + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+                if (i < M && bq < B) {
+                    const uint32_t r = GATHER ? rows[i] : i;
+                    if (r < R) {
+                        const uint32_t p0 = (uint32_t)acc[a][4 * g + 0][v];
+                        const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
+                        const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
+                        const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
+                        out[(uint64_t)r * B + bq] =
+                            p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+using RingWide = Ring<2, 2, 2, 4, 6>;     // 128 x 256, 6 stages (144 KiB)
+
+template <class T>
+pir_status launch_gemm_ring(const pir_db_t* db, const uint32_t* rows, uint32_t M,
+                            const int8_t* QL, uint32_t Cp, uint32_t B, uint32_t N,
+                            const uint32_t* colsum, uint32_t* out, hipStream_t s) {
+    static bool attr_set = false;   // raise the dynamic LDS limit once
+    if (!attr_set) {
+        if (hipFuncSetAttribute((const void*)k_gemm_ring<T, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_gemm_ring<T, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess)
+            return PIR_ERR_DEVICE;
+        attr_set = true;
+    }
+    const uint32_t n_tiles = (N + T::BN - 1) / T::BN;
+    const uint32_t m_tiles = (M + T::BM - 1) / T::BM;
+    const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
+    if (rows)
+        k_gemm_ring<T, true><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+            db->D, db->pitch, R, C, rows, M, QL, Cp, B, n_tiles, m_tiles, colsum, db->rowterm, out);
+    else
+        k_gemm_ring<T, false><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+            db->D, db->pitch, R, C, rows, M, QL, Cp, B, n_tiles, m_tiles, colsum, db->rowterm, out);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
 // Tile shapes: small batches (one group of 32 queries) use 4 waves along M;
 // larger ones a 2 x 2 wave grid of 64 x 128 wave tiles.
 using TileNarrow = Tile<4, 1, 1, 4, 128>;   // 128 x 128
@@ -337,7 +573,10 @@ pir_status mfma_answer_batch(const pir_db_t* db, const uint32_t* Q, uint32_t B, 
 
     const uint32_t M = rows ? m : (uint32_t)db->rows;
     if (M == 0) return PIR_OK;
+    const bool ring_ok = db->aligned && (C % 16 == 0);
     if (L.N <= 128)
         return launch_gemm<TileNarrow>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
+    if (ring_ok)
+        return launch_gemm_ring<RingWide>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
     return launch_gemm<TileWide>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
 }
