@@ -53,7 +53,9 @@ typedef enum pir_status {
     PIR_ERR_NO_MEMORY = 3,     /* device or host allocation failed */
     PIR_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
     PIR_ERR_UNSUPPORTED = 5,   /* device is not gfx950 */
-    PIR_ERR_WORKSPACE = 6      /* workspace missing, too small or misaligned */
+    PIR_ERR_WORKSPACE = 6,     /* workspace missing, too small or misaligned */
+    PIR_ERR_BUSY = 7,          /* serving queue full: request not admitted */
+    PIR_ERR_TIMEOUT = 8        /* wait ended before the request completed */
 } pir_status;
 
 /* A hipStream_t, passed as an opaque pointer. */
@@ -132,6 +134,20 @@ pir_status pir_answer_batch(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint3
                             void* d_ws, size_t ws_bytes, pir_stream_t stream);
 
 /*
+ * Batched Answer in query-major layout: query b is the contiguous row
+ * Qt[b][0..C) and its answer the contiguous row outT[b][0..R), i.e.
+ * outT[b][r] = sum_j D[r][j] * Qt[b][j] mod 2^32.  Same kernels and results
+ * as pir_answer_batch; the layout lets a server pack and unpack individual
+ * queries with plain copies.
+ *
+ *   d_Qt    B x C words, row-major.   d_outT  B x R words, row-major.
+ *   d_ws    workspace of pir_workspace_bytes(db, B) bytes.
+ */
+pir_status pir_answer_batch_qmajor(pir_db_t* db, const uint32_t* d_Qt, uint32_t B,
+                                   uint32_t* d_outT, void* d_ws, size_t ws_bytes,
+                                   pir_stream_t stream);
+
+/*
  * Offline hint: H = D A mod 2^32 (the client-independent part of the
  * response, moved off the online path as in Section 5.3).
  *
@@ -168,6 +184,105 @@ pir_status pir_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
 pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
                                 const uint32_t* d_A, uint32_t n, uint32_t* d_H,
                                 void* d_ws, size_t ws_bytes, pir_stream_t stream);
+
+/*
+ * Kernel variants (tile shapes, pipeline depths, rows per wave) for the
+ * autotuner.  `batch` == 0 names the single-query path, `batch` >= 1 the
+ * batched path.  Variant 0 is the library's built-in choice.  Every variant
+ * computes the same exact result; only speed differs.
+ */
+uint32_t pir_variant_count(uint32_t batch);
+/* Static name of a variant ("invalid" when out of range); never NULL. */
+const char* pir_variant_name(uint32_t batch, uint32_t variant);
+/*
+ * Use `variant` for calls on `db` whose batch size falls in the same
+ * power-of-two bucket as `batch` (batch == 0: pir_answer).  Returns
+ * PIR_ERR_UNSUPPORTED when the variant cannot serve that bucket on this
+ * database (e.g. a pipelined kernel on an unaligned database), leaving the
+ * previous choice in place.  Not synchronized with calls in flight on other
+ * threads.
+ */
+pir_status pir_db_set_variant(pir_db_t* db, uint32_t batch, uint32_t variant);
+uint32_t pir_db_get_variant(const pir_db_t* db, uint32_t batch);
+
+/*
+ * Serving loop: continuous batching of queries over resident databases
+ * (the batched, latency-oriented response of Section 5.2).  Host-side
+ * queues feed per-database slots (stream, pinned staging, device buffers);
+ * a scheduler thread launches whatever has queued whenever a slot is free,
+ * as one HIP-graph replay per batch (sizes rounded up to powers of two), and
+ * admits a batch only if its device bytes fit the memory budget next to the
+ * batches already in flight.  Latency runs from the request's (scheduled)
+ * arrival time to its answer being in the caller's host buffer.
+ */
+typedef struct pir_server pir_server_t;
+
+typedef struct pir_server_config {
+    uint32_t max_batch;         /* largest batch per launch: power of two, 1..1024 */
+    uint32_t slots_per_db;      /* batches in flight per database, 1..16 */
+    uint64_t mem_budget_bytes;  /* device bytes of all batches in flight (queries,
+                                   answers, workspace), > 0 */
+    uint32_t max_queue;         /* queued requests per database before submit
+                                   returns PIR_ERR_BUSY; 0 = unbounded */
+    uint32_t use_graphs;        /* 1: replay captured HIP graphs; 0: direct launches */
+} pir_server_config;
+
+typedef struct pir_server_stats {
+    uint64_t submitted, completed, failed, rejected;
+    uint64_t batches, batched_queries;           /* launched batches and their queries */
+    uint64_t budget_bytes, peak_inflight_bytes;  /* admission budget and its high-water mark */
+    uint64_t p50_ns, p99_ns, max_ns;             /* latency of completed requests */
+} pir_server_stats;
+
+/* Create a server on the current device (no threads yet). */
+pir_status pir_server_create(const pir_server_config* cfg, pir_server_t** out);
+/* Register an open database (borrowed; keep it open until destroy).  Only
+ * before pir_server_start.  *db_index receives its index. */
+pir_status pir_server_add_db(pir_server_t* server, pir_db_t* db, uint32_t* db_index);
+/* Allocate slots, capture the graphs and start the scheduler and completion
+ * threads.  PIR_ERR_NO_MEMORY if a single query of some database does not
+ * fit the budget or an allocation fails. */
+pir_status pir_server_start(pir_server_t* server);
+/*
+ * Queue one query (C words, host memory) for database `db_index`.  The
+ * answer (R words) is copied to `h_answer` (host; NULL discards it) when the
+ * request completes.  Both buffers must stay valid until then.
+ * `t_arrival_ns` is the arrival time on pir_server_now_ns()'s clock (0 =
+ * now).  *ticket identifies the request.  PIR_ERR_BUSY if the queue is full.
+ */
+pir_status pir_server_submit(pir_server_t* server, uint32_t db_index, const uint32_t* h_q,
+                             uint32_t* h_answer, uint64_t t_arrival_ns, uint64_t* ticket);
+/* Monotonic clock used for arrival times, nanoseconds. */
+uint64_t pir_server_now_ns(void);
+/* Block until the request completes (PIR_OK), fails (PIR_ERR_DEVICE) or
+ * `timeout_ns` passes (PIR_ERR_TIMEOUT; UINT64_MAX waits forever). */
+pir_status pir_server_wait(pir_server_t* server, uint64_t ticket, uint64_t timeout_ns);
+/* Block until every submitted request has completed or failed. */
+pir_status pir_server_drain(pir_server_t* server);
+/* Stop launching batches for one database and wait for its batches in
+ * flight, e.g. around pir_update_rows / pir_hint_update_rows; queued
+ * requests wait.  pir_server_resume_db restarts it. */
+pir_status pir_server_pause_db(pir_server_t* server, uint32_t db_index);
+pir_status pir_server_resume_db(pir_server_t* server, uint32_t db_index);
+/* Counters and latency percentiles so far. */
+pir_status pir_server_stats_get(pir_server_t* server, pir_server_stats* out);
+/* Latencies (ns; 0 = not completed) of tickets first .. first+count-1. */
+pir_status pir_server_latencies(pir_server_t* server, uint64_t first, uint64_t count,
+                                uint64_t* out_ns);
+/*
+ * Open-loop load generator: submit request i at offsets_ns[i] after the
+ * call starts (scheduled time = arrival time), for database db_index[i],
+ * query h_q[i] and answer buffer h_answer[i] (h_answer may be NULL).
+ * Returns after the last submission; *first_ticket is the first accepted
+ * ticket (UINT64_MAX if none).  Rejected (queue full) requests are counted
+ * in the stats and skipped.
+ */
+pir_status pir_server_replay(pir_server_t* server, uint64_t n, const uint64_t* offsets_ns,
+                             const uint32_t* db_index, const uint32_t* const* h_q,
+                             uint32_t* const* h_answer, uint64_t* first_ticket);
+/* Finish every queued and running request, stop the threads and free the
+ * server's buffers (not the databases). */
+pir_status pir_server_destroy(pir_server_t* server);
 
 #ifdef __cplusplus
 }

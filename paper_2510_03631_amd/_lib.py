@@ -21,6 +21,7 @@ PIR_OK = 0
 STATUS_NAMES = {
     0: "PIR_OK", 1: "PIR_ERR_INVALID_ARG", 2: "PIR_ERR_SHAPE", 3: "PIR_ERR_NO_MEMORY",
     4: "PIR_ERR_DEVICE", 5: "PIR_ERR_UNSUPPORTED", 6: "PIR_ERR_WORKSPACE",
+    7: "PIR_ERR_BUSY", 8: "PIR_ERR_TIMEOUT",
 }
 
 _lib = None
@@ -31,6 +32,19 @@ _U64 = ctypes.c_uint64
 _U32 = ctypes.c_uint32
 _SZ = ctypes.c_size_t
 _ST = ctypes.c_int
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("slots_per_db", ctypes.c_uint32),
+                ("mem_budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_uint32),
+                ("use_graphs", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "failed", "rejected", "batches", "batched_queries",
+        "budget_bytes", "peak_inflight_bytes", "p50_ns", "p99_ns", "max_ns")]
+
 
 # name -> (restype, argtypes); mirrors include/qpir.h
 SIGNATURES = {
@@ -45,6 +59,24 @@ SIGNATURES = {
     "pir_setup_hint": (_ST, [_P, _P, _U32, _P, _P, _SZ, _P]),
     "pir_update_rows": (_ST, [_P, _P, _U32, _P, _P]),
     "pir_hint_update_rows": (_ST, [_P, _P, _U32, _P, _U32, _P, _P, _SZ, _P]),
+    "pir_answer_batch_qmajor": (_ST, [_P, _P, _U32, _P, _P, _SZ, _P]),
+    "pir_variant_count": (_U32, [_U32]),
+    "pir_variant_name": (ctypes.c_char_p, [_U32, _U32]),
+    "pir_db_set_variant": (_ST, [_P, _U32, _U32]),
+    "pir_db_get_variant": (_U32, [_P, _U32]),
+    "pir_server_create": (_ST, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
+    "pir_server_add_db": (_ST, [_P, _P, ctypes.POINTER(_U32)]),
+    "pir_server_start": (_ST, [_P]),
+    "pir_server_submit": (_ST, [_P, _U32, _P, _P, _U64, ctypes.POINTER(_U64)]),
+    "pir_server_now_ns": (_U64, []),
+    "pir_server_wait": (_ST, [_P, _U64, _U64]),
+    "pir_server_drain": (_ST, [_P]),
+    "pir_server_pause_db": (_ST, [_P, _U32]),
+    "pir_server_resume_db": (_ST, [_P, _U32]),
+    "pir_server_stats_get": (_ST, [_P, ctypes.POINTER(ServerStats)]),
+    "pir_server_latencies": (_ST, [_P, _U64, _U64, _P]),
+    "pir_server_replay": (_ST, [_P, _U64, _P, _P, _P, _P, ctypes.POINTER(_U64)]),
+    "pir_server_destroy": (_ST, [_P]),
 }
 
 
@@ -213,6 +245,34 @@ class Database:
                                      _stream_ptr(stream, self.device)), "pir_answer_batch")
         return out
 
+    def answer_batch_qmajor(self, Qt: torch.Tensor, out: torch.Tensor = None, stream=None,
+                            ws=None):
+        """``out[b] = D Qt[b] mod 2^32`` for ``Qt`` of shape B x C
+        (``pir_answer_batch_qmajor``); ``out`` is B x R."""
+        if Qt.dim() != 2:
+            raise ValueError("Qt must be B x C")
+        B = int(Qt.shape[0])
+        qp = _ptr_words(Qt, "Qt", (B, self.cols), self.device)
+        if out is None:
+            out = torch.empty((B, self.rows), dtype=torch.int32, device=self.device)
+        op = _ptr_words(out, "out", (B, self.rows), self.device)
+        if ws is None:
+            ws = self.workspace(B)
+        wp, wn = self._ws_args(ws)
+        check(lib().pir_answer_batch_qmajor(self.handle, qp, B, op, wp, wn,
+                                            _stream_ptr(stream, self.device)),
+              "pir_answer_batch_qmajor")
+        return out
+
+    def set_variant(self, batch: int, variant) -> None:
+        """Pin a kernel variant (index or name) for ``batch``'s bucket."""
+        if isinstance(variant, str):
+            variant = variant_names(batch).index(variant)
+        check(lib().pir_db_set_variant(self.handle, batch, int(variant)), "pir_db_set_variant")
+
+    def get_variant(self, batch: int) -> int:
+        return int(lib().pir_db_get_variant(self.handle, batch))
+
     def setup_hint(self, A: torch.Tensor, out: torch.Tensor = None, stream=None, ws=None):
         """``H = D A mod 2^32`` for ``A`` of shape C x n (``pir_setup_hint``)."""
         n = int(A.shape[1])
@@ -250,3 +310,9 @@ class Database:
                                          _stream_ptr(stream, self.device)),
               "pir_hint_update_rows")
         return H
+
+
+def variant_names(batch: int) -> list:
+    """Names of the kernel variants for a batch size (0: single query)."""
+    h = lib()
+    return [h.pir_variant_name(batch, i).decode() for i in range(h.pir_variant_count(batch))]

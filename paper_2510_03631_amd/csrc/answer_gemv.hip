@@ -32,8 +32,7 @@ constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kChunk = 1024;   // columns covered by one wave-wide 16-byte load
 constexpr int kSlice = 4096;   // query words staged in LDS at a time
-constexpr int kRW = 16;        // rows per wave
-constexpr int kRowsPerBlock = kRW * kWaves;
+constexpr int kRW = 16;        // rows per wave of the default variant
 
 // Four consecutive query words -> the four limb words; limb k holds byte k
 // of each word, the first word in the low byte.
@@ -200,8 +199,8 @@ struct SplitPlan {
 
 // Split the columns only when the row blocks alone cannot give every CU
 // a workgroup.
-SplitPlan plan_splits(const pir_db_t* db) {
-    const uint64_t blocks = (db->rows + kRowsPerBlock - 1) / kRowsPerBlock;
+SplitPlan plan_splits(const pir_db_t* db, uint32_t rows_per_block) {
+    const uint64_t blocks = (db->rows + rows_per_block - 1) / rows_per_block;
     const uint64_t chunks = (db->cols + kChunk - 1) / kChunk;
     uint64_t s = 1;
     if (blocks < 256) s = (512 + blocks - 1) / blocks;
@@ -212,35 +211,72 @@ SplitPlan plan_splits(const pir_db_t* db) {
     return SplitPlan{(uint32_t)s, (uint32_t)cps};
 }
 
-}  // namespace
-
-size_t gemv_workspace_bytes(const pir_db_t* db) {
-    const SplitPlan p = plan_splits(db);
+size_t split_bytes(const pir_db_t* db, uint32_t rows_per_block) {
+    const SplitPlan p = plan_splits(db, rows_per_block);
     return p.splits > 1 ? round_up((size_t)p.splits * db->rows * 4, kWsAlign) : 0;
 }
 
-pir_status gemv_answer(const pir_db_t* db, const uint32_t* q, uint32_t* a, void* ws,
-                       size_t ws_bytes, hipStream_t s) {
-    const SplitPlan p = plan_splits(db);
+template <int RW>
+pir_status launch_answer1(const pir_db_t* db, const uint32_t* q, uint32_t* a, void* ws,
+                          size_t ws_bytes, hipStream_t s) {
+    constexpr uint32_t kRows = RW * kWaves;
+    const SplitPlan p = plan_splits(db, kRows);
     const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
     uint32_t* dst = a;
     if (p.splits > 1) {
-        if (!ws || ws_bytes < gemv_workspace_bytes(db) || ((uintptr_t)ws % kWsAlign))
+        if (!ws || ws_bytes < split_bytes(db, kRows) || ((uintptr_t)ws % kWsAlign))
             return PIR_ERR_WORKSPACE;
         dst = static_cast<uint32_t*>(ws);
     }
     const bool vec = db->aligned && ((uintptr_t)q % 16 == 0);
-    dim3 grid((R + kRowsPerBlock - 1) / kRowsPerBlock, p.splits);
+    dim3 grid((R + kRows - 1) / kRows, p.splits);
     if (vec)
-        k_answer1<kRW, true><<<grid, kThreads, 0, s>>>(db->D, db->pitch, R, C, q, dst,
-                                                       p.cols_per_split);
+        k_answer1<RW, true><<<grid, kThreads, 0, s>>>(db->D, db->pitch, R, C, q, dst,
+                                                      p.cols_per_split);
     else
-        k_answer1<kRW, false><<<grid, kThreads, 0, s>>>(db->D, db->pitch, R, C, q, dst,
-                                                        p.cols_per_split);
+        k_answer1<RW, false><<<grid, kThreads, 0, s>>>(db->D, db->pitch, R, C, q, dst,
+                                                       p.cols_per_split);
     PIR_LAUNCH_CHECK();
     if (p.splits > 1) {
         k_sum_splits<<<(R + 255) / 256, 256, 0, s>>>(dst, R, p.splits, a);
         PIR_LAUNCH_CHECK();
     }
     return PIR_OK;
+}
+
+struct GemvVariant {
+    const char* name;
+    uint32_t rows_per_wave;
+    pir_status (*launch)(const pir_db_t*, const uint32_t*, uint32_t*, void*, size_t, hipStream_t);
+};
+
+const GemvVariant kGemv[] = {
+    {"auto", kRW, launch_answer1<kRW>},
+    {"rows16", 16, launch_answer1<16>},
+    {"rows8", 8, launch_answer1<8>},
+    {"rows32", 32, launch_answer1<32>},
+};
+constexpr uint32_t kNumGemv = sizeof(kGemv) / sizeof(kGemv[0]);
+
+}  // namespace
+
+uint32_t gemv_variant_count() { return kNumGemv; }
+
+const char* gemv_variant_name(uint32_t v) { return v < kNumGemv ? kGemv[v].name : nullptr; }
+
+// Enough for every variant, so a workspace sized once serves any tuning.
+size_t gemv_workspace_bytes(const pir_db_t* db) {
+    size_t m = 0;
+    for (uint32_t v = 0; v < kNumGemv; ++v) {
+        const size_t b = split_bytes(db, kGemv[v].rows_per_wave * kWaves);
+        m = b > m ? b : m;
+    }
+    return m;
+}
+
+pir_status gemv_answer(const pir_db_t* db, const uint32_t* q, uint32_t* a, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
+    uint32_t v = db->variant[0];
+    if (v >= kNumGemv) v = 0;
+    return kGemv[v].launch(db, q, a, ws, ws_bytes, s);
 }

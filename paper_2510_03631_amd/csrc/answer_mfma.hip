@@ -47,24 +47,37 @@ __global__ void k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
     if (i < n) p[i] = 0;
 }
 
-// Block: 64 query coordinates j x 32 queries b.  Reads Q coalesced along b,
-// transposes through LDS, writes 4 limb rows x 64 bytes per query.
-__global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, uint32_t C,
-                                                uint32_t B, uint32_t Cp,
+// Block: 64 query coordinates j x 32 queries b.  Element (j, b) of the
+// query matrix is Q[j * ldj + b * ldb].  The load is coalesced along b for
+// the row-major layout (ldb == 1) and along j for the query-major one
+// (QMAJOR, ldj == 1); both go through an LDS tile, then each thread writes
+// 32 limb bytes of one query.
+template <bool QMAJOR>
+__global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, uint64_t ldj,
+                                                uint64_t ldb, uint32_t C, uint32_t B, uint32_t Cp,
                                                 int8_t* __restrict__ QL,
                                                 uint32_t* __restrict__ colsum) {
     __shared__ uint32_t s[32][65];
     const int t = threadIdx.x;
     const uint32_t j0 = blockIdx.x * 64u;
     const uint32_t b0 = blockIdx.y * 32u;
-    {
+    if (QMAJOR) {
+        const int bb = t >> 3;
+        const uint32_t b = b0 + bb;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int jj = (t & 7) * 8 + p;
+            const uint32_t j = j0 + jj;
+            s[bb][jj] = (j < C && b < B) ? Q[(uint64_t)j * ldj + (uint64_t)b * ldb] : 0u;
+        }
+    } else {
         const int bb = t & 31;
         const uint32_t b = b0 + bb;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             const int jj = (t >> 5) + 8 * p;
             const uint32_t j = j0 + jj;
-            s[bb][jj] = (j < C && b < B) ? Q[(uint64_t)j * B + b] : 0u;
+            s[bb][jj] = (j < C && b < B) ? Q[(uint64_t)j * ldj + (uint64_t)b * ldb] : 0u;
         }
     }
     __syncthreads();
@@ -135,7 +148,8 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
                                               uint32_t B, uint32_t n_tiles,
                                               const uint32_t* __restrict__ colsum,
                                               const uint32_t* __restrict__ rowterm,
-                                              uint32_t* __restrict__ out) {
+                                              uint32_t* __restrict__ out, uint64_t o_ldr,
+                                              uint64_t o_ldb) {
     __shared__ __attribute__((aligned(16))) uint8_t sA[T::BM * T::LDK];
     __shared__ __attribute__((aligned(16))) uint8_t sB[T::BN * T::LDK];
 
@@ -257,7 +271,7 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
                         const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
                         const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
                         const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
-                        out[(uint64_t)r * B + bq] =
+                        out[(uint64_t)r * o_ldr + (uint64_t)bq * o_ldb] =
                             p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
                     }
                 }
@@ -323,7 +337,8 @@ __global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D
                                                    uint32_t B, uint32_t n_tiles, uint32_t m_tiles,
                                                    const uint32_t* __restrict__ colsum,
                                                    const uint32_t* __restrict__ rowterm,
-                                                   uint32_t* __restrict__ out) {
+                                                   uint32_t* __restrict__ out, uint64_t o_ldr,
+                                                   uint64_t o_ldb) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -463,7 +478,7 @@ __global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D
                         const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
                         const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
                         const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
-                        out[(uint64_t)r * B + bq] =
+                        out[(uint64_t)r * o_ldr + (uint64_t)bq * o_ldb] =
                             p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
                     }
                 }
@@ -472,62 +487,114 @@ __global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D
     }
 }
 
-using RingWide = Ring<2, 2, 2, 4, 6>;     // 128 x 256, 6 stages (144 KiB)
+// ---------------------------------------------------------------- dispatch
+struct Gemm {
+    const pir_db_t* db;
+    const uint32_t* rows;   // gathered rows or null
+    uint32_t M;             // output rows
+    const int8_t* QL;
+    uint32_t Cp, B, N;
+    const uint32_t* colsum;
+    uint32_t* out;
+    uint64_t o_ldr, o_ldb;
+};
 
 template <class T>
-pir_status launch_gemm_ring(const pir_db_t* db, const uint32_t* rows, uint32_t M,
-                            const int8_t* QL, uint32_t Cp, uint32_t B, uint32_t N,
-                            const uint32_t* colsum, uint32_t* out, hipStream_t s) {
-    static bool attr_set = false;   // raise the dynamic LDS limit once
-    if (!attr_set) {
-        if (hipFuncSetAttribute((const void*)k_gemm_ring<T, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_gemm_ring<T, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess)
-            return PIR_ERR_DEVICE;
-        attr_set = true;
-    }
-    const uint32_t n_tiles = (N + T::BN - 1) / T::BN;
-    const uint32_t m_tiles = (M + T::BM - 1) / T::BM;
+pir_status launch_ring(const Gemm& g, hipStream_t s) {
+    const uint32_t n_tiles = (g.N + T::BN - 1) / T::BN;
+    const uint32_t m_tiles = (g.M + T::BM - 1) / T::BM;
     const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    const pir_db_t* db = g.db;
     const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
-    if (rows)
+    if (g.rows)
         k_gemm_ring<T, true><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
-            db->D, db->pitch, R, C, rows, M, QL, Cp, B, n_tiles, m_tiles, colsum, db->rowterm, out);
+            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
+            db->rowterm, g.out, g.o_ldr, g.o_ldb);
     else
         k_gemm_ring<T, false><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
-            db->D, db->pitch, R, C, rows, M, QL, Cp, B, n_tiles, m_tiles, colsum, db->rowterm, out);
+            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
+            db->rowterm, g.out, g.o_ldr, g.o_ldb);
     PIR_LAUNCH_CHECK();
     return PIR_OK;
 }
 
-// Tile shapes: small batches (one group of 32 queries) use 4 waves along M;
-// larger ones a 2 x 2 wave grid of 64 x 128 wave tiles.
-using TileNarrow = Tile<4, 1, 1, 4, 128>;   // 128 x 128
-using TileWide = Tile<2, 2, 2, 4, 128>;     // 128 x 256
+template <class T>
+pir_status set_ring_lds() {
+    if (hipFuncSetAttribute((const void*)k_gemm_ring<T, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_gemm_ring<T, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess)
+        return PIR_ERR_DEVICE;
+    return PIR_OK;
+}
 
 template <class T>
-pir_status launch_gemm(const pir_db_t* db, const uint32_t* rows, uint32_t M, const int8_t* QL,
-                       uint32_t Cp, uint32_t B, uint32_t N, const uint32_t* colsum,
-                       uint32_t* out, hipStream_t s) {
-    const uint32_t n_tiles = (N + T::BN - 1) / T::BN;
-    const uint32_t m_tiles = (M + T::BM - 1) / T::BM;
+pir_status launch_reg(const Gemm& g, hipStream_t s) {
+    const uint32_t n_tiles = (g.N + T::BN - 1) / T::BN;
+    const uint32_t m_tiles = (g.M + T::BM - 1) / T::BM;
     const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    const pir_db_t* db = g.db;
     const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
-#define PIR_GEMM(VEC, GATHER)                                                              \
-    k_gemm<T, VEC, GATHER><<<(uint32_t)blocks, 256, 0, s>>>(db->D, db->pitch, R, C, rows, M, \
-                                                             QL, Cp, B, n_tiles, colsum,      \
-                                                             db->rowterm, out)
+#define PIR_GEMM(VEC, GATHER)                                                                \
+    k_gemm<T, VEC, GATHER><<<(uint32_t)blocks, 256, 0, s>>>(db->D, db->pitch, R, C, g.rows, g.M, \
+                                                             g.QL, g.Cp, g.B, n_tiles, g.colsum, \
+                                                             db->rowterm, g.out, g.o_ldr, g.o_ldb)
     if (db->aligned) {
-        if (rows) PIR_GEMM(true, true); else PIR_GEMM(true, false);
+        if (g.rows) PIR_GEMM(true, true); else PIR_GEMM(true, false);
     } else {
-        if (rows) PIR_GEMM(false, true); else PIR_GEMM(false, false);
+        if (g.rows) PIR_GEMM(false, true); else PIR_GEMM(false, false);
     }
 #undef PIR_GEMM
     PIR_LAUNCH_CHECK();
     return PIR_OK;
+}
+
+// Kernel variants of the batched product.  Ring variants need a 16-byte
+// aligned database with C a multiple of 16; 256-wide tiles need N a
+// multiple of 256 (batches above 32 queries, padded to 64).
+using Ring128x256S6 = Ring<2, 2, 2, 4, 6>;   // 144 KiB LDS
+using Ring128x256S4 = Ring<2, 2, 2, 4, 4>;   //  96 KiB
+using Ring256x256S4 = Ring<2, 2, 4, 4, 4>;   // 128 KiB, 128x128 per wave
+using Ring128x128S8 = Ring<4, 1, 1, 4, 8>;   // 128 KiB
+using Reg128x256 = Tile<2, 2, 2, 4, 128>;
+using Reg128x128 = Tile<4, 1, 1, 4, 128>;
+
+struct VariantInfo {
+    const char* name;
+    bool ring;
+    uint32_t bn;
+    pir_status (*launch)(const Gemm&, hipStream_t);
+};
+
+const VariantInfo kVariants[] = {
+    {"auto", false, 0, nullptr},
+    {"ring_128x256_s6", true, 256, launch_ring<Ring128x256S6>},
+    {"ring_128x256_s4", true, 256, launch_ring<Ring128x256S4>},
+    {"ring_256x256_s4", true, 256, launch_ring<Ring256x256S4>},
+    {"ring_128x128_s8", true, 128, launch_ring<Ring128x128S8>},
+    {"reg_128x256", false, 256, launch_reg<Reg128x256>},
+    {"reg_128x128", false, 128, launch_reg<Reg128x128>},
+};
+constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+bool ring_ok(const pir_db_t* db) { return db->aligned && (db->cols % 16 == 0); }
+
+uint32_t padded_batch(uint32_t B) { return B <= 32u ? 32u : (B + 63u) / 64u * 64u; }
+
+bool variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
+    if (v == 0) return true;
+    if (v >= kNumVariants) return false;
+    const VariantInfo& vi = kVariants[v];
+    if (vi.ring && !ring_ok(db)) return false;
+    return (4u * padded_batch(B)) % vi.bn == 0;
+}
+
+uint32_t default_variant(const pir_db_t* db, uint32_t B) {
+    const bool narrow = padded_batch(B) == 32u;
+    if (ring_ok(db)) return narrow ? 4u : 1u;
+    return narrow ? 6u : 5u;
 }
 
 struct BatchLayout {
@@ -537,9 +604,9 @@ struct BatchLayout {
 
 BatchLayout batch_layout(const pir_db_t* db, uint32_t B) {
     BatchLayout L;
-    // One group of 32 queries uses the 128-wide tile; larger batches are
+    // One group of 32 queries uses a 128-wide tile; larger batches are
     // padded to whole 256-wide tiles (64 queries).  Padded queries are zero.
-    L.Bp = B <= 32u ? 32u : (B + 63u) / 64u * 64u;
+    L.Bp = padded_batch(B);
     L.N = 4u * L.Bp;
     L.Cp = (uint32_t)round_up(db->cols, kKPad);
     L.ql_bytes = round_up((size_t)L.N * L.Cp, kWsAlign);
@@ -550,12 +617,28 @@ BatchLayout batch_layout(const pir_db_t* db, uint32_t B) {
 
 }  // namespace
 
+pir_status mfma_init() {
+    pir_status st;
+    if ((st = set_ring_lds<Ring128x256S6>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring128x256S4>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring256x256S4>()) != PIR_OK) return st;
+    return set_ring_lds<Ring128x128S8>();
+}
+
+uint32_t mfma_variant_count() { return kNumVariants; }
+
+const char* mfma_variant_name(uint32_t v) { return v < kNumVariants ? kVariants[v].name : nullptr; }
+
+bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
+    return variant_valid(db, B, v);
+}
+
 size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B) {
     if (B == 0) return 0;
     return batch_layout(db, B).total;
 }
 
-pir_status mfma_answer_batch(const pir_db_t* db, const uint32_t* Q, uint32_t B, uint32_t* out,
+pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
                              const uint32_t* rows, uint32_t m, void* ws, size_t ws_bytes,
                              hipStream_t s) {
     const BatchLayout L = batch_layout(db, B);
@@ -568,15 +651,16 @@ pir_status mfma_answer_batch(const pir_db_t* db, const uint32_t* Q, uint32_t B, 
     k_zero_words<<<(L.Bp + 255) / 256, 256, 0, s>>>(colsum, L.Bp);
     PIR_LAUNCH_CHECK();
     dim3 ig(L.Cp / 64, L.Bp / 32);
-    k_ingest<<<ig, 256, 0, s>>>(Q, C, B, L.Cp, QL, colsum);
+    if (io.q_ldj == 1)
+        k_ingest<true><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Cp, QL, colsum);
+    else
+        k_ingest<false><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Cp, QL, colsum);
     PIR_LAUNCH_CHECK();
 
     const uint32_t M = rows ? m : (uint32_t)db->rows;
     if (M == 0) return PIR_OK;
-    const bool ring_ok = db->aligned && (C % 16 == 0);
-    if (L.N <= 128)
-        return launch_gemm<TileNarrow>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
-    if (ring_ok)
-        return launch_gemm_ring<RingWide>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
-    return launch_gemm<TileWide>(db, rows, M, QL, L.Cp, B, L.N, colsum, out, s);
+    uint32_t v = db->variant[batch_bucket(B)];
+    if (!variant_valid(db, B, v) || v == 0) v = default_variant(db, B);
+    const Gemm g{db, rows, M, QL, L.Cp, B, L.N, colsum, io.out, io.o_ldr, io.o_ldb};
+    return kVariants[v].launch(g, s);
 }

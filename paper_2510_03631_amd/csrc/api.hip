@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, handle lifecycle and dispatch.
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "qpir_internal.h"
@@ -11,6 +12,13 @@ bool device_is_gfx950(int dev) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
     return strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+pir_status init_once() {
+    static std::once_flag once;
+    static pir_status st = PIR_OK;
+    std::call_once(once, [] { st = mfma_init(); });
+    return st;
 }
 
 // Calls must run with the handle's device current.
@@ -32,6 +40,8 @@ const char* pir_status_string(pir_status status) {
         case PIR_ERR_DEVICE: return "device error";
         case PIR_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
         case PIR_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+        case PIR_ERR_BUSY: return "queue full";
+        case PIR_ERR_TIMEOUT: return "timed out";
     }
     return "unknown status";
 }
@@ -46,6 +56,7 @@ pir_status pir_db_open(uint8_t* d_D, uint64_t rows, uint64_t cols, uint64_t row_
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return PIR_ERR_DEVICE;
     if (!device_is_gfx950(dev)) return PIR_ERR_UNSUPPORTED;
+    if (init_once() != PIR_OK) return PIR_ERR_DEVICE;
 
     pir_db_t* db = new (std::nothrow) pir_db_t();
     if (!db) return PIR_ERR_NO_MEMORY;
@@ -112,16 +123,30 @@ pir_status pir_answer_batch(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint3
     if (!db_ok(db)) return PIR_ERR_INVALID_ARG;
     if (B == 0) return PIR_OK;
     if (!d_Q || !d_out || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
-    if (B > (1u << 20)) return PIR_ERR_SHAPE;
-    return mfma_answer_batch(db, d_Q, B, d_out, nullptr, 0, d_ws, ws_bytes,
+    if (B > kMaxBatch) return PIR_ERR_SHAPE;
+    const BatchIO io{d_Q, B, 1, d_out, B, 1};
+    return mfma_answer_batch(db, io, B, nullptr, 0, d_ws, ws_bytes,
+                             static_cast<hipStream_t>(stream));
+}
+
+pir_status pir_answer_batch_qmajor(pir_db_t* db, const uint32_t* d_Qt, uint32_t B,
+                                   uint32_t* d_outT, void* d_ws, size_t ws_bytes,
+                                   pir_stream_t stream) {
+    if (!db_ok(db)) return PIR_ERR_INVALID_ARG;
+    if (B == 0) return PIR_OK;
+    if (!d_Qt || !d_outT || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
+    if (B > kMaxBatch) return PIR_ERR_SHAPE;
+    const BatchIO io{d_Qt, 1, db->cols, d_outT, 1, db->rows};
+    return mfma_answer_batch(db, io, B, nullptr, 0, d_ws, ws_bytes,
                              static_cast<hipStream_t>(stream));
 }
 
 pir_status pir_setup_hint(pir_db_t* db, const uint32_t* d_A, uint32_t n, uint32_t* d_H,
                           void* d_ws, size_t ws_bytes, pir_stream_t stream) {
     if (!db_ok(db) || !d_A || !d_H || n == 0 || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
-    if (n > (1u << 20)) return PIR_ERR_SHAPE;
-    return mfma_answer_batch(db, d_A, n, d_H, nullptr, 0, d_ws, ws_bytes,
+    if (n > kMaxBatch) return PIR_ERR_SHAPE;
+    const BatchIO io{d_A, n, 1, d_H, n, 1};
+    return mfma_answer_batch(db, io, n, nullptr, 0, d_ws, ws_bytes,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -144,9 +169,37 @@ pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m
     if (m == 0) return PIR_OK;
     if (!d_rows || !d_A || !d_H || n == 0 || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (m > db->rows) return PIR_ERR_SHAPE;
-    if (n > (1u << 20)) return PIR_ERR_SHAPE;
-    return mfma_answer_batch(db, d_A, n, d_H, d_rows, m, d_ws, ws_bytes,
+    if (n > kMaxBatch) return PIR_ERR_SHAPE;
+    const BatchIO io{d_A, n, 1, d_H, n, 1};
+    return mfma_answer_batch(db, io, n, d_rows, m, d_ws, ws_bytes,
                              static_cast<hipStream_t>(stream));
+}
+
+uint32_t pir_variant_count(uint32_t batch) {
+    return batch == 0 ? gemv_variant_count() : mfma_variant_count();
+}
+
+const char* pir_variant_name(uint32_t batch, uint32_t variant) {
+    const char* n = batch == 0 ? gemv_variant_name(variant) : mfma_variant_name(variant);
+    return n ? n : "invalid";
+}
+
+pir_status pir_db_set_variant(pir_db_t* db, uint32_t batch, uint32_t variant) {
+    if (!db_ok(db)) return PIR_ERR_INVALID_ARG;
+    if (batch > kMaxBatch) return PIR_ERR_SHAPE;
+    if (batch == 0) {
+        if (variant >= gemv_variant_count()) return PIR_ERR_INVALID_ARG;
+    } else {
+        if (variant >= mfma_variant_count()) return PIR_ERR_INVALID_ARG;
+        if (!mfma_variant_valid(db, batch, variant)) return PIR_ERR_UNSUPPORTED;
+    }
+    db->variant[batch_bucket(batch)] = (uint8_t)variant;
+    return PIR_OK;
+}
+
+uint32_t pir_db_get_variant(const pir_db_t* db, uint32_t batch) {
+    if (!db_ok(db) || batch > kMaxBatch) return 0;
+    return db->variant[batch_bucket(batch)];
 }
 
 }  // extern "C"

@@ -7,6 +7,8 @@
 
 #include "qpir.h"
 
+constexpr int kBuckets = 24;   // batch-size buckets: 0 = single query, k = B in (2^(k-2), 2^(k-1)]
+
 struct pir_db {
     uint32_t magic;        // kDbMagic while open
     uint8_t* D;            // borrowed database bytes
@@ -14,11 +16,13 @@ struct pir_db {
     uint32_t* rowterm;     // device, rows words: 0x80808080 * sum_j D[r][j]
     int device;
     bool aligned;          // D and pitch are multiples of 16
+    uint8_t variant[kBuckets];   // kernel variant per batch bucket (0 = built-in choice)
 };
 
 constexpr uint32_t kDbMagic = 0x51504952u;   // "QPIR"
 constexpr uint64_t kMaxDim = (1ull << 31) - 1;
 constexpr size_t kWsAlign = 256;
+constexpr uint32_t kMaxBatch = 1u << 20;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -26,12 +30,33 @@ inline bool db_ok(const pir_db_t* db) { return db && db->magic == kDbMagic; }
 
 inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Bucket of a batch size: 0 for the single-query entry point (batch == 0),
+// otherwise 1 + ceil(log2(B)).
+inline int batch_bucket(uint32_t batch) {
+    if (batch == 0) return 0;
+    int k = 0;
+    while ((1u << k) < batch && k < 31) ++k;
+    return k + 1 < kBuckets ? k + 1 : kBuckets - 1;
+}
+
 #define PIR_LAUNCH_CHECK()                                   \
     do {                                                     \
         if (hipGetLastError() != hipSuccess) return PIR_ERR_DEVICE; \
     } while (0)
 
+// Query matrix and answer matrix of a batched call, as word strides:
+// query b word j at Q[j * q_ldj + b * q_ldb]; answer b row r at
+// out[r * o_ldr + b * o_ldb].
+struct BatchIO {
+    const uint32_t* Q;
+    uint64_t q_ldj, q_ldb;
+    uint32_t* out;
+    uint64_t o_ldr, o_ldb;
+};
+
 // ---- single-query path (answer_gemv.hip)
+uint32_t gemv_variant_count();
+const char* gemv_variant_name(uint32_t v);
 size_t gemv_workspace_bytes(const pir_db_t* db);
 pir_status gemv_answer(const pir_db_t* db, const uint32_t* q, uint32_t* a, void* ws,
                        size_t ws_bytes, hipStream_t s);
@@ -42,7 +67,11 @@ pir_status launch_scatter_rows(const pir_db_t* db, const uint32_t* rows, uint32_
                                const uint8_t* src, hipStream_t s);
 
 // ---- batched / hint path (answer_mfma.hip)
+pir_status mfma_init();
+uint32_t mfma_variant_count();
+const char* mfma_variant_name(uint32_t v);
+bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v);
 size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B);
-pir_status mfma_answer_batch(const pir_db_t* db, const uint32_t* Q, uint32_t B, uint32_t* out,
+pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
                              const uint32_t* rows, uint32_t m, void* ws, size_t ws_bytes,
                              hipStream_t s);

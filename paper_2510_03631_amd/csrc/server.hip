@@ -1,0 +1,550 @@
+// Serving loop: continuous batching of PIR queries over resident databases.
+//
+// The paper's parallelization goal is to cut the servers' online response
+// latency under concurrent demand, answering queries in batches over a
+// database kept in GPU memory (Section 5.2; Figure 3 reports end-to-end
+// delay against the number of users).  This file is the host runtime around
+// the Answer kernels that does that on one GPU:
+//
+// * every registered database owns `slots_per_db` slots: a stream, pinned
+//   host staging for queries and answers, device buffers and a workspace
+//   sized for the largest batch;
+// * a scheduler thread turns each database's queue into batches as soon as
+//   one of its slots is free: whatever arrived while earlier batches were on
+//   the GPU joins the next batch (continuous batching), up to `max_batch`;
+// * admission is by memory: a batch is launched only if its device
+//   footprint (queries, answers, workspace) fits in what `mem_budget_bytes`
+//   leaves after the batches already in flight; otherwise it waits, and a
+//   smaller batch is formed when that fits;
+// * batch sizes are rounded up to powers of two; for every (slot, size) the
+//   copy-in, kernels and copy-out were captured once into a HIP graph at
+//   start, so a launch is one graph replay (padded queries are ignored);
+// * batches for different databases run on different streams and overlap
+//   on the device;
+// * a poller thread completes batches in any order, copies each answer to
+//   its caller's buffer and records the latency from the scheduled arrival
+//   time (open-loop: queueing delay is included).
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "qpir_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               Clock::now().time_since_epoch()).count();
+}
+
+enum ReqState : int { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
+
+struct Req {
+    uint32_t db = 0;
+    const uint32_t* h_q = nullptr;
+    uint32_t* h_ans = nullptr;
+    uint64_t t_arrival = 0, t_done = 0;
+    std::atomic<int> state{kQueued};
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint32_t* h_Q = nullptr;   // pinned, max_batch x C (query-major)
+    uint32_t* h_O = nullptr;   // pinned, max_batch x R (answer-major)
+    uint32_t* d_Q = nullptr;
+    uint32_t* d_O = nullptr;
+    void* d_ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<hipGraph_t> graph;
+    std::vector<hipGraphExec_t> exec;
+    std::vector<Req*> batch;
+    uint32_t size = 0;         // padded batch size in flight
+    uint64_t cost = 0;         // budget bytes held while in flight
+    uint32_t db = 0;           // owning database index
+    bool busy = false;
+};
+
+struct DbQueue {
+    pir_db_t* db = nullptr;
+    uint64_t R = 0, C = 0;
+    std::deque<Req*> queue;
+    std::vector<Slot> slots;
+    bool paused = false;
+    uint32_t inflight = 0;
+};
+
+uint32_t log2_floor(uint32_t x) {
+    uint32_t k = 0;
+    while ((2u << k) <= x) ++k;
+    return k;
+}
+
+uint32_t pow2_ceil(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct pir_server {
+    pir_server_config cfg{};
+    int device = -1;
+    std::vector<DbQueue> dbs;
+    std::deque<Req> reqs;               // index = ticket
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done;
+    std::thread sched, poller;
+    std::vector<Slot*> inflight;
+    bool started = false, stopping = false;
+    pir_status fault = PIR_OK;
+    uint64_t used = 0, peak = 0;
+    uint64_t n_batches = 0, n_batched = 0, n_done = 0, n_failed = 0, n_rejected = 0;
+    uint32_t rr = 0;                    // round-robin start over databases
+
+    uint64_t batch_cost(const DbQueue& d, uint32_t size) const {
+        const size_t ws = size == 1 ? pir_workspace_bytes(d.db, 0) : pir_workspace_bytes(d.db, size);
+        return (uint64_t)size * (d.R + d.C) * 4u + ws;
+    }
+
+    pir_status enqueue(DbQueue& d, Slot& s, uint32_t size) {
+        hipStream_t st = s.stream;
+        if (hipMemcpyAsync(s.d_Q, s.h_Q, (size_t)size * d.C * 4, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+            return PIR_ERR_DEVICE;
+        pir_status r = size == 1
+                           ? pir_answer(d.db, s.d_Q, s.d_O, s.d_ws, s.ws_bytes, st)
+                           : pir_answer_batch_qmajor(d.db, s.d_Q, size, s.d_O, s.d_ws, s.ws_bytes, st);
+        if (r != PIR_OK) return r;
+        if (hipMemcpyAsync(s.h_O, s.d_O, (size_t)size * d.R * 4, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+            return PIR_ERR_DEVICE;
+        return PIR_OK;
+    }
+
+    pir_status setup_slot(DbQueue& d, Slot& s) {
+        const uint32_t mb = cfg.max_batch;
+        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+            return PIR_ERR_DEVICE;
+        if (hipHostMalloc((void**)&s.h_Q, (size_t)mb * d.C * 4, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&s.h_O, (size_t)mb * d.R * 4, hipHostMallocDefault) != hipSuccess)
+            return PIR_ERR_NO_MEMORY;
+        memset(s.h_Q, 0, (size_t)mb * d.C * 4);
+        s.ws_bytes = std::max(pir_workspace_bytes(d.db, 0),
+                              mb > 1 ? pir_workspace_bytes(d.db, mb) : (size_t)0);
+        if (hipMalloc((void**)&s.d_Q, (size_t)mb * d.C * 4) != hipSuccess ||
+            hipMalloc((void**)&s.d_O, (size_t)mb * d.R * 4) != hipSuccess ||
+            (s.ws_bytes && hipMalloc(&s.d_ws, s.ws_bytes) != hipSuccess))
+            return PIR_ERR_NO_MEMORY;
+        if (hipMemset(s.d_Q, 0, (size_t)mb * d.C * 4) != hipSuccess) return PIR_ERR_DEVICE;
+        const uint32_t nb = log2_floor(mb) + 1;
+        s.graph.assign(nb, nullptr);
+        s.exec.assign(nb, nullptr);
+        if (!cfg.use_graphs) return PIR_OK;
+        for (uint32_t k = 0; k < nb; ++k) {
+            if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return PIR_ERR_DEVICE;
+            pir_status r = enqueue(d, s, 1u << k);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(s.stream, &g);
+            if (r != PIR_OK) return r;
+            if (e != hipSuccess || !g) return PIR_ERR_DEVICE;
+            s.graph[k] = g;
+            if (hipGraphInstantiate(&s.exec[k], g, nullptr, nullptr, 0) != hipSuccess)
+                return PIR_ERR_DEVICE;
+            // One replay now, so first requests do not pay for lazy setup.
+            if (hipGraphLaunch(s.exec[k], s.stream) != hipSuccess) return PIR_ERR_DEVICE;
+        }
+        return hipStreamSynchronize(s.stream) == hipSuccess ? PIR_OK : PIR_ERR_DEVICE;
+    }
+
+    void release_slot(Slot& s) {
+        for (auto e : s.exec) if (e) (void)hipGraphExecDestroy(e);
+        for (auto g : s.graph) if (g) (void)hipGraphDestroy(g);
+        s.exec.clear();
+        s.graph.clear();
+        if (s.d_ws) (void)hipFree(s.d_ws);
+        if (s.d_Q) (void)hipFree(s.d_Q);
+        if (s.d_O) (void)hipFree(s.d_O);
+        if (s.h_Q) (void)hipHostFree(s.h_Q);
+        if (s.h_O) (void)hipHostFree(s.h_O);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+        s = Slot();
+    }
+
+    // Fail every request of a batch (device error); caller holds the lock.
+    void fail_batch(Slot& s) {
+        for (Req* r : s.batch) {
+            r->state.store(kFailed, std::memory_order_release);
+            ++n_failed;
+        }
+        s.batch.clear();
+    }
+
+    void scheduler_loop() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            bool launched = false;
+            const size_t nd = dbs.size();
+            for (size_t step = 0; step < nd && fault == PIR_OK; ++step) {
+                DbQueue& d = dbs[(rr + step) % nd];
+                while (!d.queue.empty() && !d.paused) {
+                    Slot* s = nullptr;
+                    for (auto& x : d.slots)
+                        if (!x.busy) { s = &x; break; }
+                    if (!s) break;
+                    uint32_t n = (uint32_t)std::min<size_t>(d.queue.size(), cfg.max_batch);
+                    uint32_t size = pow2_ceil(n);
+                    while (size > 1 && used + batch_cost(d, size) > cfg.mem_budget_bytes) size >>= 1;
+                    if (used + batch_cost(d, size) > cfg.mem_budget_bytes) break;   // wait
+                    n = std::min(n, size);
+                    s->batch.assign(d.queue.begin(), d.queue.begin() + n);
+                    d.queue.erase(d.queue.begin(), d.queue.begin() + n);
+                    s->busy = true;
+                    s->size = size;
+                    s->cost = batch_cost(d, size);
+                    used += s->cost;
+                    peak = std::max(peak, used);
+                    ++d.inflight;
+                    ++n_batches;
+                    n_batched += n;
+                    for (Req* r : s->batch) r->state.store(kRunning, std::memory_order_relaxed);
+                    lk.unlock();
+                    // Pack the queries (query-major rows of C words) and launch.
+                    for (uint32_t b = 0; b < n; ++b)
+                        memcpy(s->h_Q + (size_t)b * d.C, s->batch[b]->h_q, d.C * 4);
+                    pir_status st = PIR_OK;
+                    if (cfg.use_graphs) {
+                        if (hipGraphLaunch(s->exec[log2_floor(size)], s->stream) != hipSuccess)
+                            st = PIR_ERR_DEVICE;
+                    } else {
+                        st = enqueue(d, *s, size);
+                    }
+                    if (st == PIR_OK && hipEventRecord(s->done, s->stream) != hipSuccess)
+                        st = PIR_ERR_DEVICE;
+                    lk.lock();
+                    if (st != PIR_OK) {
+                        fault = st;
+                        fail_batch(*s);
+                        s->busy = false;
+                        used -= s->cost;
+                        --d.inflight;
+                        cv_done.notify_all();
+                        break;
+                    }
+                    inflight.push_back(s);
+                    launched = true;
+                    cv_done.notify_all();
+                }
+            }
+            rr = nd ? (rr + 1) % (uint32_t)nd : 0;
+            if (fault != PIR_OK) {   // fail whatever is queued
+                for (auto& d : dbs) {
+                    for (Req* r : d.queue) {
+                        r->state.store(kFailed, std::memory_order_release);
+                        ++n_failed;
+                    }
+                    d.queue.clear();
+                }
+                cv_done.notify_all();
+            }
+            if (stopping && inflight.empty()) {
+                bool empty = true;
+                for (auto& d : dbs) empty = empty && d.queue.empty();
+                if (empty || fault != PIR_OK) break;
+            }
+            if (!launched) cv_sched.wait(lk);
+        }
+    }
+
+    void complete(Slot* s) {
+        DbQueue* d = &dbs[s->db];
+        const uint64_t t = now_ns();
+        for (size_t b = 0; b < s->batch.size(); ++b) {
+            Req* r = s->batch[b];
+            if (r->h_ans) memcpy(r->h_ans, s->h_O + b * d->R, d->R * 4);
+            r->t_done = t;
+            r->state.store(kDone, std::memory_order_release);
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        n_done += s->batch.size();
+        s->batch.clear();
+        s->busy = false;
+        used -= s->cost;
+        --d->inflight;
+        inflight.erase(std::find(inflight.begin(), inflight.end(), s));
+        cv_sched.notify_all();
+        cv_done.notify_all();
+    }
+
+    void poller_loop() {
+        (void)hipSetDevice(device);
+        std::vector<Slot*> watch;
+        uint64_t idle_since = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_done.wait(lk, [&] { return !inflight.empty() || (stopping && sched_done); });
+                if (inflight.empty() && stopping && sched_done) break;
+                watch = inflight;
+            }
+            bool any = false;
+            for (Slot* s : watch) {
+                const hipError_t e = hipEventQuery(s->done);
+                if (e == hipSuccess) {
+                    complete(s);
+                    any = true;
+                } else if (e != hipErrorNotReady) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    fault = PIR_ERR_DEVICE;
+                    fail_batch(*s);
+                    s->busy = false;
+                    used -= s->cost;
+                    --dbs[s->db].inflight;
+                    inflight.erase(std::find(inflight.begin(), inflight.end(), s));
+                    cv_sched.notify_all();
+                    cv_done.notify_all();
+                }
+            }
+            // Spin briefly for low completion latency, then back off.
+            if (any) {
+                idle_since = 0;
+            } else {
+                const uint64_t t = now_ns();
+                if (!idle_since) idle_since = t;
+                if (t - idle_since < 200000) std::this_thread::yield();
+                else std::this_thread::sleep_for(std::chrono::microseconds(20));
+            }
+        }
+    }
+
+    bool sched_done = false;
+};
+
+extern "C" {
+
+pir_status pir_server_create(const pir_server_config* cfg, pir_server_t** out) {
+    if (!cfg || !out) return PIR_ERR_INVALID_ARG;
+    if (cfg->max_batch == 0 || cfg->max_batch > 1024 || (cfg->max_batch & (cfg->max_batch - 1)) ||
+        cfg->slots_per_db == 0 || cfg->slots_per_db > 16 || cfg->mem_budget_bytes == 0)
+        return PIR_ERR_SHAPE;
+    pir_server_t* s = new (std::nothrow) pir_server_t();
+    if (!s) return PIR_ERR_NO_MEMORY;
+    s->cfg = *cfg;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return PIR_ERR_DEVICE;
+    }
+    *out = s;
+    return PIR_OK;
+}
+
+pir_status pir_server_add_db(pir_server_t* s, pir_db_t* db, uint32_t* db_index) {
+    if (!s || !db_ok(db) || !db_index) return PIR_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->started) return PIR_ERR_INVALID_ARG;
+    if (db->device != s->device) return PIR_ERR_INVALID_ARG;
+    DbQueue d;
+    d.db = db;
+    d.R = db->rows;
+    d.C = db->cols;
+    s->dbs.push_back(std::move(d));
+    *db_index = (uint32_t)(s->dbs.size() - 1);
+    return PIR_OK;
+}
+
+pir_status pir_server_start(pir_server_t* s) {
+    if (!s) return PIR_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->started || s->dbs.empty()) return PIR_ERR_INVALID_ARG;
+    for (auto& d : s->dbs) {
+        if (s->batch_cost(d, 1) > s->cfg.mem_budget_bytes) return PIR_ERR_NO_MEMORY;
+        d.slots.resize(s->cfg.slots_per_db);
+        for (auto& sl : d.slots) {
+            sl.db = (uint32_t)(&d - &s->dbs[0]);
+            pir_status st = s->setup_slot(d, sl);
+            if (st != PIR_OK) {
+                for (auto& dd : s->dbs)
+                    for (auto& x : dd.slots) s->release_slot(x);
+                return st;
+            }
+        }
+    }
+    s->started = true;
+    s->sched = std::thread([s] { s->scheduler_loop(); });
+    s->poller = std::thread([s] { s->poller_loop(); });
+    return PIR_OK;
+}
+
+pir_status pir_server_submit(pir_server_t* s, uint32_t db_index, const uint32_t* h_q,
+                             uint32_t* h_answer, uint64_t t_arrival_ns, uint64_t* ticket) {
+    if (!s || !h_q || !ticket) return PIR_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->started || s->stopping) return PIR_ERR_INVALID_ARG;
+    if (db_index >= s->dbs.size()) return PIR_ERR_INVALID_ARG;
+    if (s->fault != PIR_OK) return s->fault;
+    DbQueue& d = s->dbs[db_index];
+    if (s->cfg.max_queue && d.queue.size() >= s->cfg.max_queue) {
+        ++s->n_rejected;
+        return PIR_ERR_BUSY;
+    }
+    s->reqs.emplace_back();
+    Req& r = s->reqs.back();
+    r.db = db_index;
+    r.h_q = h_q;
+    r.h_ans = h_answer;
+    r.t_arrival = t_arrival_ns ? t_arrival_ns : now_ns();
+    *ticket = s->reqs.size() - 1;
+    d.queue.push_back(&r);
+    s->cv_sched.notify_all();
+    return PIR_OK;
+}
+
+uint64_t pir_server_now_ns(void) { return now_ns(); }
+
+pir_status pir_server_wait(pir_server_t* s, uint64_t ticket, uint64_t timeout_ns) {
+    if (!s) return PIR_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (ticket >= s->reqs.size()) return PIR_ERR_INVALID_ARG;
+    Req& r = s->reqs[ticket];
+    auto done = [&] { return r.state.load(std::memory_order_acquire) >= kDone; };
+    if (timeout_ns == UINT64_MAX) {
+        s->cv_done.wait(lk, done);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done)) {
+        return PIR_ERR_TIMEOUT;
+    }
+    return r.state.load(std::memory_order_acquire) == kDone ? PIR_OK : PIR_ERR_DEVICE;
+}
+
+pir_status pir_server_drain(pir_server_t* s) {
+    if (!s) return PIR_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->n_done + s->n_failed >= s->reqs.size(); });
+    return s->n_failed ? PIR_ERR_DEVICE : PIR_OK;
+}
+
+pir_status pir_server_pause_db(pir_server_t* s, uint32_t db_index) {
+    if (!s) return PIR_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (db_index >= s->dbs.size()) return PIR_ERR_INVALID_ARG;
+    DbQueue& d = s->dbs[db_index];
+    d.paused = true;
+    s->cv_done.wait(lk, [&] { return d.inflight == 0; });
+    return PIR_OK;
+}
+
+pir_status pir_server_resume_db(pir_server_t* s, uint32_t db_index) {
+    if (!s) return PIR_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (db_index >= s->dbs.size()) return PIR_ERR_INVALID_ARG;
+    s->dbs[db_index].paused = false;
+    s->cv_sched.notify_all();
+    return PIR_OK;
+}
+
+pir_status pir_server_stats_get(pir_server_t* s, pir_server_stats* out) {
+    if (!s || !out) return PIR_ERR_INVALID_ARG;
+    std::vector<uint64_t> lat;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        memset(out, 0, sizeof(*out));
+        out->submitted = s->reqs.size();
+        out->completed = s->n_done;
+        out->failed = s->n_failed;
+        out->rejected = s->n_rejected;
+        out->batches = s->n_batches;
+        out->batched_queries = s->n_batched;
+        out->budget_bytes = s->cfg.mem_budget_bytes;
+        out->peak_inflight_bytes = s->peak;
+        lat.reserve(s->n_done);
+        for (auto& r : s->reqs)
+            if (r.state.load(std::memory_order_acquire) == kDone) lat.push_back(r.t_done - r.t_arrival);
+    }
+    if (!lat.empty()) {
+        std::sort(lat.begin(), lat.end());
+        auto q = [&](double f) { return lat[std::min(lat.size() - 1, (size_t)(f * lat.size()))]; };
+        out->p50_ns = q(0.50);
+        out->p99_ns = q(0.99);
+        out->max_ns = lat.back();
+    }
+    return PIR_OK;
+}
+
+pir_status pir_server_latencies(pir_server_t* s, uint64_t first, uint64_t count, uint64_t* out_ns) {
+    if (!s || (!out_ns && count)) return PIR_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (first + count > s->reqs.size()) return PIR_ERR_SHAPE;
+    for (uint64_t i = 0; i < count; ++i) {
+        const Req& r = s->reqs[first + i];
+        out_ns[i] = r.state.load(std::memory_order_acquire) == kDone ? r.t_done - r.t_arrival : 0;
+    }
+    return PIR_OK;
+}
+
+pir_status pir_server_replay(pir_server_t* s, uint64_t n, const uint64_t* offsets_ns,
+                             const uint32_t* db_index, const uint32_t* const* h_q,
+                             uint32_t* const* h_answer, uint64_t* first_ticket) {
+    if (!s || !offsets_ns || !db_index || !h_q || !first_ticket) return PIR_ERR_INVALID_ARG;
+    const uint64_t t0 = now_ns();
+    bool first = true;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t due = t0 + offsets_ns[i];
+        for (;;) {   // sleep until ~100 us before the arrival, then spin
+            const uint64_t t = now_ns();
+            if (t >= due) break;
+            if (due - t > 150000) std::this_thread::sleep_for(std::chrono::nanoseconds(due - t - 100000));
+        }
+        uint64_t tk = 0;
+        pir_status st = pir_server_submit(s, db_index[i], h_q[i], h_answer ? h_answer[i] : nullptr,
+                                          due, &tk);
+        if (st == PIR_ERR_BUSY) continue;   // counted as rejected
+        if (st != PIR_OK) return st;
+        if (first) {
+            *first_ticket = tk;
+            first = false;
+        }
+    }
+    if (first) *first_ticket = UINT64_MAX;
+    return PIR_OK;
+}
+
+pir_status pir_server_destroy(pir_server_t* s) {
+    if (!s) return PIR_OK;
+    pir_status st = PIR_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        s->cv_sched.notify_all();
+    }
+    if (s->sched.joinable()) s->sched.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->sched_done = true;
+        s->cv_done.notify_all();
+    }
+    if (s->poller.joinable()) s->poller.join();
+    if (s->fault != PIR_OK) st = s->fault;
+    for (auto& d : s->dbs)
+        for (auto& x : d.slots) {
+            if (x.stream) (void)hipStreamSynchronize(x.stream);
+            s->release_slot(x);
+        }
+    delete s;
+    return st;
+}
+
+}  // extern "C"
