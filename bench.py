@@ -95,6 +95,78 @@ def cpu_baseline(R: int, C: int, seconds: float = 10.0):
                       f"{n} passes in {el:.1f} s (plain C loops, OpenMP)"}
 
 
+def serving_run(srv, t_off, which, qs) -> dict:
+    """Replay one open-loop trace; latency percentiles and throughput."""
+    import numpy as np
+    s0 = srv.stats()
+    t0 = time.perf_counter()
+    first = srv.replay((t_off * 1e9).astype(np.uint64), which, qs)
+    srv.drain()
+    wall = time.perf_counter() - t0
+    s1 = srv.stats()
+    n = s1["completed"] - s0["completed"]
+    lat = srv.latencies(first, n).astype(np.float64) / 1e6
+    batches = s1["batches"] - s0["batches"]
+    return {"offered_qps": round(len(t_off) / float(t_off[-1]), 1) if len(t_off) else 0.0,
+            "achieved_qps": round(n / wall, 1), "queries": int(n),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "max_ms": round(float(lat.max()), 3),
+            "mean_batch": round((s1["batched_queries"] - s0["batched_queries"]) / max(batches, 1), 2),
+            "rejected": int(s1["rejected"] - s0["rejected"])}
+
+
+def serving_bench(args) -> dict:
+    """Eight regional databases resident in HBM, Poisson arrivals, database
+    picked by Zipf(1.1) in listed order; continuous batching with HIP-graph
+    batches against the plain one-query-per-launch path."""
+    import numpy as np
+    import torch
+    import paper_2510_03631_amd as qp
+    from paper_2510_03631_amd import tune
+    from paper_2510_03631_amd.serve import Server
+    import workload
+    dev = torch.device("cuda:0")
+    Ds, dbs = [], []
+    for k, (R, C) in enumerate(workload.SERVING_DBS):
+        Ds.append(workload.device_db(R, C, workload.SEED_BASE + 30 + k, dev))
+        dbs.append(qp.Database(Ds[-1]))
+        tune.apply(dbs[-1])
+    g = workload.rng(workload.SEED_BASE + 3)
+    pool = [[workload.uniform_u32(g, C) for _ in range(16)] for (R, C) in workload.SERVING_DBS]
+
+    def trace(rate, seconds, seed):
+        gg = workload.rng(seed)
+        t = workload.poisson_arrivals(gg, rate, seconds)
+        which = workload.zipf_choice(gg, len(dbs), len(t))
+        pick = gg.integers(0, 16, size=len(t))
+        return t, which, [pool[d][i] for d, i in zip(which, pick)]
+
+    out = {"databases": [f"{R}x{C}" for R, C in workload.SERVING_DBS],
+           "db_bytes": int(sum(R * C for R, C in workload.SERVING_DBS)),
+           "budget_bytes": 2 << 30}
+    budget = 2 << 30
+    with Server(dbs, max_batch=64, slots_per_db=2, mem_budget_bytes=budget) as srv:
+        t, w, qs = trace(workload.SERVING_RATE, 1.0, 1)
+        serving_run(srv, t, w, qs)                       # warm-up
+        t, w, qs = trace(workload.SERVING_RATE, args.serving_seconds, 2)
+        out["at_2000qps"] = serving_run(srv, t, w, qs)
+        sweep = []
+        for rate in (8000.0, 20000.0, 40000.0):
+            t, w, qs = trace(rate, 2.0, int(rate))
+            sweep.append(serving_run(srv, t, w, qs))
+        out["batched_sweep"] = sweep
+    with Server(dbs, max_batch=1, slots_per_db=2, mem_budget_bytes=budget) as srv:
+        plain = []
+        for rate in (2000.0, 8000.0, 20000.0):
+            t, w, qs = trace(rate, 2.0, int(rate) + 1)
+            plain.append(serving_run(srv, t, w, qs))
+        out["plain_sweep"] = plain
+    for db in dbs:
+        db.close()
+    return out
+
+
 def profile_mode(args, dev, stream) -> int:
     """One kernel family on the headline database, for counter runs.
 
@@ -104,21 +176,25 @@ def profile_mode(args, dev, stream) -> int:
     """
     import torch
     import paper_2510_03631_amd as qp
+    from paper_2510_03631_amd import tune
     import workload
     shape = workload.CONFIGS["spectrum_1q"]
     R, C, n = shape.rows, shape.cols, shape.n
     if args.profile == "calibrate":
         x = workload.device_u32((1 << 28,), workload.SEED_BASE + 9, dev)
         y = torch.empty_like(x)
-        for _ in range(args.warmup + args.steps):
+        for _ in range(args.warmup):
             y.copy_(x)
-            torch.neg(x, out=y)
-        torch.cuda.synchronize()
+        wall, ev = time_on_stream(lambda: y.copy_(x), args.steps, stream)
+        t = ev / args.steps
         print(json.dumps({"profile": "calibrate", "bytes_read": x.numel() * 4,
-                          "bytes_written": x.numel() * 4, "steps": args.steps}))
+                          "bytes_written": x.numel() * 4, "steps": args.steps,
+                          "copy_us": round(t * 1e6, 2),
+                          "copy_gbs_read_plus_write": round(2 * x.numel() * 4 / t / 1e9, 1)}))
         return 0
     D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
     db = qp.Database(D)
+    tune.apply(db)
     if args.profile == "answer":
         q = workload.device_u32((C,), workload.SEED_BASE + 2, dev)
         a = torch.empty(R, dtype=torch.int32, device=dev)
@@ -151,6 +227,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--profile", choices=["answer", "batch", "hint", "calibrate"],
                     help="run only one kernel family (for rocprofv3 runs) and exit")
     args = ap.parse_args()
@@ -163,6 +241,7 @@ def main() -> int:
     import torch
 
     import paper_2510_03631_amd as qp
+    from paper_2510_03631_amd import tune
     import workload
 
     dev = torch.device("cuda:0")
@@ -176,6 +255,7 @@ def main() -> int:
     log(f"drawing {R}x{C} database on the device")
     D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
     db = qp.Database(D)
+    tune.apply(db)
     # One LWE query.  The client's query is A s + e + Delta u_i; timing the
     # answer does not depend on its value, and under LWE it is
     # indistinguishable from uniform, so the bench draws the words directly
@@ -257,10 +337,18 @@ def main() -> int:
                           "mfma_frac": round(8.0 * R * C * n / th / 1e12 / INT8_PEAK_TOPS, 4)}
         del A, H, Q, out
 
+    if not args.no_serving:
+        log("serving: 8 resident databases, Poisson arrivals, Zipf(1.1)")
+        db.close()
+        del D
+        torch.cuda.empty_cache()
+        result["serving"] = serving_bench(args)
+
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ~10 s")
         result["cpu_baseline"] = cpu_baseline(R, C)
-    db.close()
+    if db._h is not None:
+        db.close()
     print(json.dumps(result), flush=True)
     return 0
 

@@ -487,6 +487,194 @@ __global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D
     }
 }
 
+// ---------------------------------------------------------------- GEMM, split load roles
+// Vector-memory loads of one wave complete in order, so a wave that feeds
+// both the D stream (HBM, long latency) and the query stream (L2, short
+// latency) can only run as far ahead as the shorter ring allows.  Here waves
+// 0-1 load only D tiles into a deep ring of SA stages and waves 2-3 load only
+// query tiles into a ring of SB stages; each wave waits on its own counter,
+// then all four meet at the barrier and compute.
+template <int WM_, int WN_, int TM_, int TN_, int SA_, int SB_>
+struct Split {
+    static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, SA = SA_, SB = SB_;
+    static constexpr int BK = 64;
+    static constexpr int BM = WM * TM * 32;
+    static constexpr int BN = WN * TN * 32;
+    static constexpr int A_BYTES = BM * BK;
+    static constexpr int B_BYTES = BN * BK;
+    static constexpr int A_LOADS = BM / 16 / 2;          // per loader wave per tile
+    static constexpr int B_LOADS = BN / 16 / 2;
+    static constexpr int LDS_BYTES = SA * A_BYTES + SB * B_BYTES;
+    static_assert(WM * WN == 4, "four waves");
+    static_assert(TN % 4 == 0, "a wave covers whole groups of four limbs");
+    static_assert(SA >= 2 && SB >= 2, "at least double buffering");
+    static_assert((SA - 2) * A_LOADS < 64 && (SB - 2) * B_LOADS < 64, "vmcnt range");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+template <class T, bool GATHER>
+__global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ D, uint64_t pitch,
+                                                    uint32_t R, uint32_t C,
+                                                    const uint32_t* __restrict__ rows, uint32_t M,
+                                                    const int8_t* __restrict__ QL, uint32_t Cp,
+                                                    uint32_t B, uint32_t n_tiles, uint32_t m_tiles,
+                                                    const uint32_t* __restrict__ colsum,
+                                                    const uint32_t* __restrict__ rowterm,
+                                                    uint32_t* __restrict__ out, uint64_t o_ldr,
+                                                    uint64_t o_ldb) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / T::WN;
+    const int wn = wave % T::WN;
+    const bool loads_d = wave < 2;
+    const int lw = wave & 1;                               // index among the loader pair
+
+    uint32_t bid = blockIdx.x;
+    {
+        const uint32_t per = gridDim.x / 8u;
+        if (bid < per * 8u) bid = (bid % 8u) * per + bid / 8u;
+    }
+    constexpr uint32_t kGroup = 8;
+    const uint32_t group = bid / (kGroup * n_tiles);
+    const uint32_t first_m = group * kGroup;
+    const uint32_t gsize = min(m_tiles - first_m, kGroup);
+    const uint32_t in_group = bid % (kGroup * n_tiles);
+    const uint32_t tile_m = first_m + in_group % gsize;
+    const uint32_t tile_n = in_group / gsize;
+    const uint32_t m0 = tile_m * T::BM;
+    const uint32_t n0 = tile_n * T::BN;
+
+    constexpr int NL = T::A_LOADS > T::B_LOADS ? T::A_LOADS : T::B_LOADS;
+    const int nl = loads_d ? T::A_LOADS : T::B_LOADS;
+    const uint8_t* src[NL];
+    uint32_t seg_off[NL];
+    const int lrow = lane >> 2;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int kb = lw + 2 * i;                         // 1 KiB block within the tile
+        const int r = kb * 16 + lrow;
+        const int seg = (lane & 3) ^ ((r >> 1) & 3);
+        seg_off[i] = 16u * seg;
+        if (loads_d) {
+            uint32_t mi = m0 + (uint32_t)min(r, T::BM - 1);
+            mi = mi < M ? mi : M - 1;
+            uint32_t dr = GATHER ? rows[mi] : mi;
+            dr = dr < R ? dr : R - 1;
+            src[i] = D + (uint64_t)dr * pitch + seg_off[i];
+        } else {
+            src[i] = reinterpret_cast<const uint8_t*>(QL) +
+                     (uint64_t)(n0 + (uint32_t)min(r, T::BN - 1)) * Cp + seg_off[i];
+        }
+    }
+    const uint32_t ktiles = (C + T::BK - 1) / T::BK;
+    uint8_t* ringA = smem;
+    uint8_t* ringB = smem + T::SA * T::A_BYTES;
+
+    auto issue = [&](uint32_t t) {
+        const uint32_t k0 = t * T::BK;
+        if (loads_d) {
+            uint8_t* stage = ringA + (t % T::SA) * T::A_BYTES;
+#pragma unroll
+            for (int i = 0; i < T::A_LOADS; ++i) {
+                uint8_t* dst = stage + (lw + 2 * i) * 1024;
+                if (k0 + seg_off[i] + 16 <= C)
+                    __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + k0), (lds_void_t*)dst,
+                                                     16, 0, 0);
+            }
+        } else {
+            uint8_t* stage = ringB + (t % T::SB) * T::B_BYTES;
+#pragma unroll
+            for (int i = 0; i < T::B_LOADS; ++i) {
+                uint8_t* dst = stage + (lw + 2 * i) * 1024;
+                __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + k0), (lds_void_t*)dst,
+                                                 16, 0, 0);
+            }
+        }
+    };
+
+    i32x16 acc[T::TM][T::TN];
+#pragma unroll
+    for (int a = 0; a < T::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < T::TN; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
+
+    const int frow = lane & 31;
+    const int fseg = lane >> 5;
+    const u32x4 centre = u32x4{kCentreWord, kCentreWord, kCentreWord, kCentreWord};
+
+    const int depth = loads_d ? T::SA : T::SB;
+    for (int p = 0; p < depth - 1; ++p)
+        if ((uint32_t)p < ktiles) issue(p);
+
+    for (uint32_t t = 0; t < ktiles; ++t) {
+        // Each loader wave waits for its own part of tile t (see k_gemm_ring
+        // for the counting; only D loads of the last tile can be skipped).
+        if (loads_d) {
+            if (t + T::SA - 1 < ktiles) wait_vmcnt<(T::SA - 2) * T::A_LOADS>();
+            else wait_vmcnt<0>();
+        } else {
+            if (t + T::SB - 1 < ktiles) wait_vmcnt<(T::SB - 2) * T::B_LOADS>();
+            else wait_vmcnt<0>();
+        }
+        ring_barrier();
+        if (t + depth - 1 < ktiles) issue(t + depth - 1);
+
+        const uint8_t* sa = ringA + (t % T::SA) * T::A_BYTES;
+        const uint8_t* sb = ringB + (t % T::SB) * T::B_BYTES;
+#pragma unroll
+        for (int ks = 0; ks < T::BK / 32; ++ks) {
+            const int seg = 2 * ks + fseg;
+            i32x4 fa[T::TM], fb[T::TN];
+#pragma unroll
+            for (int a = 0; a < T::TM; ++a) {
+                const int r = wm * T::TM * 32 + a * 32 + frow;
+                u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * slot_of(r, seg));
+                v ^= centre;
+                fa[a] = __builtin_bit_cast(i32x4, v);
+            }
+#pragma unroll
+            for (int b = 0; b < T::TN; ++b) {
+                const int r = wn * T::TN * 32 + b * 32 + frow;
+                fb[b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * slot_of(r, seg));
+            }
+#pragma unroll
+            for (int a = 0; a < T::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < T::TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+    }
+
+    const uint32_t cterm_base = C * kCentreWord;
+#pragma unroll
+    for (int g = 0; g < T::TN / 4; ++g) {
+        const uint32_t bq = (n0 + wn * T::TN * 32) / 4u + 32u * g + (uint32_t)(lane & 31);
+        const uint32_t colterm = 128u * (bq < B ? colsum[bq] - cterm_base : 0u);
+#pragma unroll
+        for (int a = 0; a < T::TM; ++a) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const uint32_t i = m0 + wm * T::TM * 32 + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+                if (i < M && bq < B) {
+                    const uint32_t r = GATHER ? rows[i] : i;
+                    if (r < R) {
+                        const uint32_t p0 = (uint32_t)acc[a][4 * g + 0][v];
+                        const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
+                        const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
+                        const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
+                        out[(uint64_t)r * o_ldr + (uint64_t)bq * o_ldb] =
+                            p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 struct Gemm {
     const pir_db_t* db;
@@ -516,6 +704,36 @@ pir_status launch_ring(const Gemm& g, hipStream_t s) {
             db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
             db->rowterm, g.out, g.o_ldr, g.o_ldb);
     PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
+template <class T>
+pir_status launch_split(const Gemm& g, hipStream_t s) {
+    const uint32_t n_tiles = (g.N + T::BN - 1) / T::BN;
+    const uint32_t m_tiles = (g.M + T::BM - 1) / T::BM;
+    const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    const pir_db_t* db = g.db;
+    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
+    if (g.rows)
+        k_gemm_split<T, true><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
+            db->rowterm, g.out, g.o_ldr, g.o_ldb);
+    else
+        k_gemm_split<T, false><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
+            db->rowterm, g.out, g.o_ldr, g.o_ldb);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
+template <class T>
+pir_status set_split_lds() {
+    if (hipFuncSetAttribute((const void*)k_gemm_split<T, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_gemm_split<T, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess)
+        return PIR_ERR_DEVICE;
     return PIR_OK;
 }
 
@@ -558,6 +776,10 @@ using Ring128x256S6 = Ring<2, 2, 2, 4, 6>;   // 144 KiB LDS
 using Ring128x256S4 = Ring<2, 2, 2, 4, 4>;   //  96 KiB
 using Ring256x256S4 = Ring<2, 2, 4, 4, 4>;   // 128 KiB, 128x128 per wave
 using Ring128x128S8 = Ring<4, 1, 1, 4, 8>;   // 128 KiB
+using Split128x256A10B4 = Split<2, 2, 2, 4, 10, 4>;   // 80 + 64 KiB
+using Split128x256A12B3 = Split<2, 2, 2, 4, 12, 3>;   // 96 + 48 KiB
+using Split256x256A5B4 = Split<2, 2, 4, 4, 5, 4>;     // 80 + 64 KiB
+using Split128x128A12B6 = Split<4, 1, 1, 4, 12, 6>;   // 96 + 48 KiB
 using Reg128x256 = Tile<2, 2, 2, 4, 128>;
 using Reg128x128 = Tile<4, 1, 1, 4, 128>;
 
@@ -576,6 +798,10 @@ const VariantInfo kVariants[] = {
     {"ring_128x128_s8", true, 128, launch_ring<Ring128x128S8>},
     {"reg_128x256", false, 256, launch_reg<Reg128x256>},
     {"reg_128x128", false, 128, launch_reg<Reg128x128>},
+    {"split_128x256_a10b4", true, 256, launch_split<Split128x256A10B4>},
+    {"split_128x256_a12b3", true, 256, launch_split<Split128x256A12B3>},
+    {"split_256x256_a5b4", true, 256, launch_split<Split256x256A5B4>},
+    {"split_128x128_a12b6", true, 128, launch_split<Split128x128A12B6>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -622,7 +848,11 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Ring128x256S6>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring128x256S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring256x256S4>()) != PIR_OK) return st;
-    return set_ring_lds<Ring128x128S8>();
+    if ((st = set_ring_lds<Ring128x128S8>()) != PIR_OK) return st;
+    if ((st = set_split_lds<Split128x256A10B4>()) != PIR_OK) return st;
+    if ((st = set_split_lds<Split128x256A12B3>()) != PIR_OK) return st;
+    if ((st = set_split_lds<Split256x256A5B4>()) != PIR_OK) return st;
+    return set_split_lds<Split128x128A12B6>();
 }
 
 uint32_t mfma_variant_count() { return kNumVariants; }
