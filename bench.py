@@ -95,6 +95,77 @@ def cpu_baseline(R: int, C: int, seconds: float = 10.0):
                       f"{n} passes in {el:.1f} s (plain C loops, OpenMP)"}
 
 
+def lwe_queries_dev(C: int, n: int, B: int, seed: int, dev):
+    """B LWE queries against a fresh uniform public matrix, built on the
+    device with pir_client_query; returns a B x C word tensor."""
+    import numpy as np
+    import torch
+    import paper_2510_03631_amd as qp
+    import workload
+    g = workload.rng(seed)
+    A = workload.device_u32((C, n), seed, dev)
+    dr = workload.lwe_draws(g, C, n, B)
+    S = torch.from_numpy(dr.s.view(np.int32)).to(dev)
+    E = torch.from_numpy(dr.e).to(dev)
+    cols = torch.from_numpy(dr.col.astype(np.uint32).view(np.int32)).to(dev)
+    Qt = qp.client_query(A, S, E, cols)
+    del A
+    return Qt
+
+
+def large_bench(stream) -> dict:
+    """131072 x 131072 database (16 GiB): 256-query batch, full hint, then a
+    refresh of 1% of the rows with the incremental hint."""
+    import torch
+    import paper_2510_03631_amd as qp
+    from paper_2510_03631_amd import tune
+    import workload
+    dev = torch.device("cuda:0")
+    shape = workload.CONFIGS["large_b256"]
+    R, C, B, n = shape.rows, shape.cols, shape.batch, shape.n
+    D = workload.device_db(R, C, workload.SEED_BASE + 4, dev)
+    db = qp.Database(D)
+    tune.apply(db)
+    Q = workload.device_u32((C, B), workload.SEED_BASE + 5, dev)
+    out = torch.empty((R, B), dtype=torch.int32, device=dev)
+    wsb = db.workspace(B)
+    fb = lambda: db.answer_batch(Q, out=out, ws=wsb)
+    fb()
+    _, evb = time_on_stream(fb, 3, stream)
+    tb = evb / 3
+    A = workload.device_u32((C, n), workload.SEED_BASE + 6, dev)
+    H = torch.empty((R, n), dtype=torch.int32, device=dev)
+    wsh = db.workspace(n)
+    fh = lambda: db.setup_hint(A, out=H, ws=wsh)
+    fh()
+    _, evh = time_on_stream(fh, 2, stream)
+    th = evh / 2
+    g = workload.rng(workload.SEED_BASE + 7)
+    m = workload.update_count(R)
+    rows = torch.from_numpy(workload.distinct_rows(g, R, m).view("int32")).to(dev)
+    new = workload.device_db(m, C, workload.SEED_BASE + 8, dev)
+    _, evu = time_on_stream(lambda: db.update_rows(rows, new), 1, stream)
+    fi = lambda: db.hint_update_rows(rows, A, H, ws=wsh)
+    fi()
+    _, evi = time_on_stream(fi, 3, stream)
+    ti = evi / 3
+    db.close()
+    res = {
+        "workload": f"{R} x {C} uint8 (16 GiB), B={B}, n={n}, refresh of {m} rows",
+        "batch_ms": round(tb * 1e3, 3), "batch_gbs_db": round(R * C / tb / 1e9, 1),
+        "batch_mfma_frac": round(8.0 * R * C * B / tb / 1e12 / INT8_PEAK_TOPS, 4),
+        "hint_ms": round(th * 1e3, 2),
+        "hint_mfma_frac": round(8.0 * R * C * n / th / 1e12 / INT8_PEAK_TOPS, 4),
+        "update_rows_ms": round(evu * 1e3, 3),
+        "incremental_hint_ms": round(ti * 1e3, 3),
+        "incremental_hint_mfma_frac": round(8.0 * m * C * n / ti / 1e12 / INT8_PEAK_TOPS, 4),
+        "hint_fraction_recomputed": round(m / R, 4),
+    }
+    del D, Q, out, A, H, new, wsb, wsh
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_run(srv, t_off, which, qs) -> dict:
     """Replay one open-loop trace; latency percentiles and throughput."""
     import numpy as np
@@ -132,8 +203,14 @@ def serving_bench(args) -> dict:
         Ds.append(workload.device_db(R, C, workload.SEED_BASE + 30 + k, dev))
         dbs.append(qp.Database(Ds[-1]))
         tune.apply(dbs[-1])
-    g = workload.rng(workload.SEED_BASE + 3)
-    pool = [[workload.uniform_u32(g, C) for _ in range(16)] for (R, C) in workload.SERVING_DBS]
+    # 16 LWE queries per database (n = 1024), built on the device by the
+    # client kernel, kept in host memory as the requests' payloads.
+    pool = []
+    for k, (R, C) in enumerate(workload.SERVING_DBS):
+        Qt = lwe_queries_dev(C, workload.LWE_N, 16, workload.SEED_BASE + 50 + k, dev)
+        host = Qt.cpu().numpy().view(np.uint32)
+        pool.append([np.ascontiguousarray(host[i]) for i in range(16)])
+        del Qt
 
     def trace(rate, seconds, seed):
         gg = workload.rng(seed)
@@ -228,6 +305,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--profile", choices=["answer", "batch", "hint", "calibrate"],
                     help="run only one kernel family (for rocprofv3 runs) and exit")
@@ -256,11 +334,9 @@ def main() -> int:
     D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
     db = qp.Database(D)
     tune.apply(db)
-    # One LWE query.  The client's query is A s + e + Delta u_i; timing the
-    # answer does not depend on its value, and under LWE it is
-    # indistinguishable from uniform, so the bench draws the words directly
-    # (the parity tests use real queries built by the client).
-    q = workload.device_u32((C,), workload.SEED_BASE + 2, dev)
+    # One LWE query q = A s + e + Delta u_i (n = 1024, sigma = 6.4), built
+    # on the device by the library's client kernel.
+    q = lwe_queries_dev(C, n, 1, workload.SEED_BASE + 2, dev)[0]
     a = torch.empty(R, dtype=torch.int32, device=dev)
     ws = db.workspace(0)
 
@@ -337,10 +413,17 @@ def main() -> int:
                           "mfma_frac": round(8.0 * R * C * n / th / 1e12 / INT8_PEAK_TOPS, 4)}
         del A, H, Q, out
 
-    if not args.no_serving:
-        log("serving: 8 resident databases, Poisson arrivals, Zipf(1.1)")
+    if not args.no_large:
+        log("large: 131072 x 131072 database, batch 256, hint, 1% refresh")
         db.close()
         del D
+        torch.cuda.empty_cache()
+        result["large_b256"] = large_bench(stream)
+
+    if not args.no_serving:
+        log("serving: 8 resident databases, Poisson arrivals, Zipf(1.1)")
+        if db._h is not None:
+            db.close()
         torch.cuda.empty_cache()
         result["serving"] = serving_bench(args)
 

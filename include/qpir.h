@@ -186,6 +186,33 @@ pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m
                                 void* d_ws, size_t ws_bytes, pir_stream_t stream);
 
 /*
+ * Client side of LWE PIR on the GPU (Definition 1: the client builds the
+ * queries and reconstructs the block from the responses), for B queries at
+ * once.  No handle needed; runs on the current device (gfx950).
+ *
+ * pir_client_query:   Qt[b][j] = sum_k A[j][k] S[b][k] + E[b][j]
+ *                                + (j == cols[b] ? 2^24 : 0)      mod 2^32
+ *   d_A     C x n words (the public matrix), row-major.
+ *   d_S     B x n words (secrets); d_E  B x C signed errors; d_cols B indices.
+ *   d_Qt    B x C words: query b is row b (the layout of
+ *           pir_answer_batch_qmajor, and of pir_answer for B == 1).
+ *
+ * pir_client_decode:  out[b][r] = ((answers[b][r] - sum_k H[r][k] S[b][k]
+ *                                   + 2^23) mod 2^32) >> 24
+ *   d_H     R x n words (the hint), row-major.
+ *   d_answers  B x R words; d_out  B x R bytes (the recovered column).
+ *
+ * Errors: PIR_ERR_INVALID_ARG (null pointer), PIR_ERR_SHAPE (zero or
+ * oversized dimension), PIR_ERR_UNSUPPORTED (device not gfx950).
+ */
+pir_status pir_client_query(const uint32_t* d_A, uint32_t C, uint32_t n, const uint32_t* d_S,
+                            const int32_t* d_E, const uint32_t* d_cols, uint32_t B,
+                            uint32_t* d_Qt, pir_stream_t stream);
+pir_status pir_client_decode(const uint32_t* d_H, uint32_t R, uint32_t n, const uint32_t* d_S,
+                             const uint32_t* d_answers, uint32_t B, uint8_t* d_out,
+                             pir_stream_t stream);
+
+/*
  * Kernel variants (tile shapes, pipeline depths, rows per wave) for the
  * autotuner.  `batch` == 0 names the single-query path, `batch` >= 1 the
  * batched path.  Variant 0 is the library's built-in choice.  Every variant

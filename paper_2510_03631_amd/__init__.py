@@ -6,6 +6,8 @@ offline hint ``H = D A``, as hand-written HIP kernels behind the C ABI in
 ``include/qpir.h``.  This package is the thin Python binding; it never
 computes on the host.
 """
-from ._lib import Database, PirError, lib, LIB_PATH, SIGNATURES  # noqa: F401
+from ._lib import (Database, PirError, lib, LIB_PATH, SIGNATURES,  # noqa: F401
+                   client_decode, client_query, variant_names)
 
-__all__ = ["Database", "PirError", "lib", "LIB_PATH", "SIGNATURES"]
+__all__ = ["Database", "PirError", "lib", "LIB_PATH", "SIGNATURES", "client_query",
+           "client_decode", "variant_names"]

@@ -77,6 +77,8 @@ SIGNATURES = {
     "pir_server_latencies": (_ST, [_P, _U64, _U64, _P]),
     "pir_server_replay": (_ST, [_P, _U64, _P, _P, _P, _P, ctypes.POINTER(_U64)]),
     "pir_server_destroy": (_ST, [_P]),
+    "pir_client_query": (_ST, [_P, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
+    "pir_client_decode": (_ST, [_P, _U32, _U32, _P, _P, _U32, _P, _P]),
 }
 
 
@@ -316,3 +318,40 @@ def variant_names(batch: int) -> list:
     """Names of the kernel variants for a batch size (0: single query)."""
     h = lib()
     return [h.pir_variant_name(batch, i).decode() for i in range(h.pir_variant_count(batch))]
+
+
+def client_query(A: torch.Tensor, S: torch.Tensor, E: torch.Tensor, cols: torch.Tensor,
+                 out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """LWE queries ``Qt[b] = A S[b] + E[b] + 2^24 u_{cols[b]}`` (B x C words)."""
+    C, n = int(A.shape[0]), int(A.shape[1])
+    B = int(S.shape[0])
+    dev = A.device
+    ap = _ptr_words(A, "A", (C, n), dev)
+    sp = _ptr_words(S, "S", (B, n), dev)
+    ep = _ptr_words(E, "E", (B, C), dev)
+    cp = _ptr_words(cols, "cols", (B,), dev)
+    if out is None:
+        out = torch.empty((B, C), dtype=torch.int32, device=dev)
+    op = _ptr_words(out, "out", (B, C), dev)
+    with torch.cuda.device(dev):
+        check(lib().pir_client_query(ap, C, n, sp, ep, cp, B, op, _stream_ptr(stream, dev)),
+              "pir_client_query")
+    return out
+
+
+def client_decode(H: torch.Tensor, S: torch.Tensor, answers: torch.Tensor,
+                  out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Recovered bytes ``((answers[b] - H S[b] + 2^23) mod 2^32) >> 24`` (B x R)."""
+    R, n = int(H.shape[0]), int(H.shape[1])
+    B = int(S.shape[0])
+    dev = H.device
+    hp = _ptr_words(H, "H", (R, n), dev)
+    sp = _ptr_words(S, "S", (B, n), dev)
+    ap = _ptr_words(answers, "answers", (B, R), dev)
+    if out is None:
+        out = torch.empty((B, R), dtype=torch.uint8, device=dev)
+    op = _ptr_bytes(out, "out", (B, R), dev)
+    with torch.cuda.device(dev):
+        check(lib().pir_client_decode(hp, R, n, sp, ap, B, op, _stream_ptr(stream, dev)),
+              "pir_client_decode")
+    return out

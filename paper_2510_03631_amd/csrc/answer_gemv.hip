@@ -8,10 +8,10 @@
 //
 // * q is split into four byte limbs, q = sum_k 2^(8k) q_k, so that
 //   a = sum_k 2^(8k) (D q_k).  Each D q_k is a sum of byte x byte products,
-//   one v_dot4_u32_u8 per four database bytes and limb: 4 VALU ops per
-//   16 database bytes per limb, ~1 op per byte overall, far under the
-//   ~4.9 lane-ops per byte the CUs can spend at full HBM rate.  The dot
-//   instruction wraps modulo 2^32, which is all the answer needs.
+//   one v_dot4_u32_u8 per four database bytes and limb, plus a shift-add
+//   per limb every 16 bytes: ~1.25 VALU lane-ops per database byte, far
+//   under the ~4.9 the CUs can spend at full HBM rate.  All arithmetic
+//   wraps modulo 2^32, which is all the answer needs.
 // * A workgroup (4 waves) stages a slice of kSlice query words in LDS as the
 //   four limb planes (split once per workgroup, not per wave).
 // * Each wave owns RW database rows.  One wave-wide 16-byte load covers 1024
@@ -61,6 +61,21 @@ __device__ inline u32x4 load16(const uint8_t* row, uint32_t c, uint32_t end) {
     return u32x4{w[0], w[1], w[2], w[3]};
 }
 
+// 16 database bytes times the matching 16 query words, mod 2^32: per limb k
+// a chain of four dot4 products (at most 16 * 255 * 255 < 2^21, exact), then
+// sum_k 2^(8k) p_k.  Combining per chunk keeps one accumulator per row.
+__device__ inline uint32_t dot16(const u32x4 d, const u32x4 L[4]) {
+    uint32_t p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t a = __builtin_amdgcn_udot4(d.x, L[k].x, 0u, false);
+        a = __builtin_amdgcn_udot4(d.y, L[k].y, a, false);
+        a = __builtin_amdgcn_udot4(d.z, L[k].z, a, false);
+        p[k] = __builtin_amdgcn_udot4(d.w, L[k].w, a, false);
+    }
+    return p[0] + (p[1] << 8) + (p[2] << 16) + (p[3] << 24);
+}
+
 template <int RW, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_answer1(const uint8_t* __restrict__ D, uint64_t pitch,
                                                       uint32_t R, uint32_t C,
@@ -72,7 +87,8 @@ __global__ __launch_bounds__(kThreads) void k_answer1(const uint8_t* __restrict_
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    // Wave-uniform, so the row addresses live in scalar registers.
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint32_t row0 = (blockIdx.x * kWaves + wave) * RW;
     const uint32_t cb = blockIdx.y * cols_per_split;
     const uint32_t ce = min(C, cb + cols_per_split);
@@ -85,11 +101,9 @@ __global__ __launch_bounds__(kThreads) void k_answer1(const uint8_t* __restrict_
         rp[i] = D + (uint64_t)r * pitch;
     }
 
-    uint32_t acc[RW][4];
+    uint32_t acc[RW];
 #pragma unroll
-    for (int i = 0; i < RW; ++i)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[i][k] = 0;
+    for (int i = 0; i < RW; ++i) acc[i] = 0;
 
     for (uint32_t s0 = cb; s0 < ce; s0 += kSlice) {
         const uint32_t se = min(ce, s0 + (uint32_t)kSlice);
@@ -136,40 +150,17 @@ __global__ __launch_bounds__(kThreads) void k_answer1(const uint8_t* __restrict_
                 for (int i = 0; i < RW; ++i)
                     d[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rp[i] + c));
 #pragma unroll
-                for (int i = 0; i < RW; ++i)
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        uint32_t a = acc[i][k];
-                        a = __builtin_amdgcn_udot4(d[i].x, L[k].x, a, false);
-                        a = __builtin_amdgcn_udot4(d[i].y, L[k].y, a, false);
-                        a = __builtin_amdgcn_udot4(d[i].z, L[k].z, a, false);
-                        a = __builtin_amdgcn_udot4(d[i].w, L[k].w, a, false);
-                        acc[i][k] = a;
-                    }
+                for (int i = 0; i < RW; ++i) acc[i] += dot16(d[i], L);
             } else if (c < se) {
 #pragma unroll
-                for (int i = 0; i < RW; ++i) {
-                    const u32x4 d = load16<VEC>(rp[i], c, se);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        uint32_t a = acc[i][k];
-                        a = __builtin_amdgcn_udot4(d.x, L[k].x, a, false);
-                        a = __builtin_amdgcn_udot4(d.y, L[k].y, a, false);
-                        a = __builtin_amdgcn_udot4(d.z, L[k].z, a, false);
-                        a = __builtin_amdgcn_udot4(d.w, L[k].w, a, false);
-                        acc[i][k] = a;
-                    }
-                }
+                for (int i = 0; i < RW; ++i) acc[i] += dot16(load16<VEC>(rp[i], c, se), L);
             }
         }
     }
 
-    // a_i = sum_k 2^(8k) acc[i][k]; then sum the 64 lanes of each row.
+    // Sum the 64 lanes of each row.
 #pragma unroll
-    for (int i = 0; i < RW; ++i) {
-        const uint32_t v = acc[i][0] + (acc[i][1] << 8) + (acc[i][2] << 16) + (acc[i][3] << 24);
-        s_red[wave][i][lane] = v;
-    }
+    for (int i = 0; i < RW; ++i) s_red[wave][i][lane] = acc[i];
     __syncthreads();
     constexpr int kLanesPerRow = 64 / RW;
     const int i = lane / kLanesPerRow;

@@ -294,6 +294,8 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 template <int WM_, int WN_, int TM_, int TN_, int STAGES_>
 struct Ring {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, STAGES = STAGES_;
+    static constexpr int NW = WM * WN;                   // waves per workgroup
+    static constexpr int THREADS = 64 * NW;
     static constexpr int BK = 64;
     static constexpr int BM = WM * TM * 32;
     static constexpr int BN = WN * TN * 32;
@@ -301,11 +303,12 @@ struct Ring {
     static constexpr int STAGE_BYTES = (BM + BN) * BK;
     static constexpr int A_BLOCKS = BM / 16;             // 1 KiB blocks of 16 rows
     static constexpr int BLOCKS = (BM + BN) / 16;
-    static constexpr int LOADS = BLOCKS / 4;             // per wave per tile
+    static constexpr int LOADS = BLOCKS / NW;            // per wave per tile
     static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
-    static_assert(WM * WN == 4, "four waves");
+    static_assert(NW == 4 || NW == 8, "four or eight waves");
     static_assert(TN % 4 == 0, "a wave covers whole groups of four limbs");
-    static_assert(BLOCKS % 4 == 0 && A_BLOCKS % 4 == 0, "blocks split evenly over waves");
+    static_assert(BLOCKS % NW == 0, "blocks split evenly over waves");
+    static_assert((STAGES - 2) * LOADS < 64, "vmcnt range");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
@@ -330,7 +333,7 @@ __device__ inline void ring_barrier() {
 }
 
 template <class T, bool GATHER>
-__global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D, uint64_t pitch,
+__global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restrict__ D, uint64_t pitch,
                                                    uint32_t R, uint32_t C,
                                                    const uint32_t* __restrict__ rows, uint32_t M,
                                                    const int8_t* __restrict__ QL, uint32_t Cp,
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D
     bool is_a[T::LOADS];
 #pragma unroll
     for (int i = 0; i < T::LOADS; ++i) {
-        const int kb = wave + 4 * i;
+        const int kb = wave + T::NW * i;
         const bool a = kb < T::A_BLOCKS;
         const int r = (a ? kb : kb - T::A_BLOCKS) * 16 + lrow;
         const int seg = (lane & 3) ^ ((r >> 1) & 3);
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D
         uint8_t* stage = smem + (t % T::STAGES) * T::STAGE_BYTES;
 #pragma unroll
         for (int i = 0; i < T::LOADS; ++i) {
-            const int kb = wave + 4 * i;
+            const int kb = wave + T::NW * i;
             uint8_t* dst = stage + kb * 1024;   // A blocks first, then B blocks
             // D segments past the last column are skipped (their LDS slots
             // keep old bytes, which meet zero query bytes); QL rows are
@@ -437,27 +440,34 @@ __global__ __launch_bounds__(256) void k_gemm_ring(const uint8_t* __restrict__ D
 
         const uint8_t* sa = smem + (t % T::STAGES) * T::STAGE_BYTES;
         const uint8_t* sb = sa + T::A_BYTES;
-#pragma unroll
-        for (int ks = 0; ks < T::BK / 32; ++ks) {
+        // Fragments of k-step ks+1 are read while the MFMAs of ks run.
+        constexpr int KS = T::BK / 32;
+        i32x4 fa[2][T::TM], fb[2][T::TN];
+        auto read_frags = [&](int ks, int buf) {
             const int seg = 2 * ks + fseg;
-            i32x4 fa[T::TM], fb[T::TN];
 #pragma unroll
             for (int a = 0; a < T::TM; ++a) {
                 const int r = wm * T::TM * 32 + a * 32 + frow;
                 u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * slot_of(r, seg));
                 v ^= centre;
-                fa[a] = __builtin_bit_cast(i32x4, v);
+                fa[buf][a] = __builtin_bit_cast(i32x4, v);
             }
 #pragma unroll
             for (int b = 0; b < T::TN; ++b) {
                 const int r = wn * T::TN * 32 + b * 32 + frow;
-                fb[b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * slot_of(r, seg));
+                fb[buf][b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * slot_of(r, seg));
             }
+        };
+        read_frags(0, 0);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks + 1 < KS) read_frags(ks + 1, (ks + 1) & 1);
 #pragma unroll
             for (int a = 0; a < T::TM; ++a)
 #pragma unroll
                 for (int b = 0; b < T::TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks & 1][a], fb[ks & 1][b],
+                                                                      acc[a][b], 0, 0, 0);
         }
     }
 
@@ -547,7 +557,6 @@ __global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ 
     const uint32_t n0 = tile_n * T::BN;
 
     constexpr int NL = T::A_LOADS > T::B_LOADS ? T::A_LOADS : T::B_LOADS;
-    const int nl = loads_d ? T::A_LOADS : T::B_LOADS;
     const uint8_t* src[NL];
     uint32_t seg_off[NL];
     const int lrow = lane >> 2;
@@ -696,11 +705,11 @@ pir_status launch_ring(const Gemm& g, hipStream_t s) {
     const pir_db_t* db = g.db;
     const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
     if (g.rows)
-        k_gemm_ring<T, true><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+        k_gemm_ring<T, true><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
             db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
             db->rowterm, g.out, g.o_ldr, g.o_ldb);
     else
-        k_gemm_ring<T, false><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+        k_gemm_ring<T, false><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
             db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
             db->rowterm, g.out, g.o_ldr, g.o_ldb);
     PIR_LAUNCH_CHECK();
@@ -776,6 +785,9 @@ using Ring128x256S6 = Ring<2, 2, 2, 4, 6>;   // 144 KiB LDS
 using Ring128x256S4 = Ring<2, 2, 2, 4, 4>;   //  96 KiB
 using Ring256x256S4 = Ring<2, 2, 4, 4, 4>;   // 128 KiB, 128x128 per wave
 using Ring128x128S8 = Ring<4, 1, 1, 4, 8>;   // 128 KiB
+using Ring8w256x256S4 = Ring<4, 2, 2, 4, 4>;  // 8 waves, 128 KiB
+using Ring8w256x256S3 = Ring<4, 2, 2, 4, 3>;  // 8 waves,  96 KiB
+using Ring8w128x256S6 = Ring<4, 2, 1, 4, 6>;  // 8 waves, 144 KiB
 using Split128x256A10B4 = Split<2, 2, 2, 4, 10, 4>;   // 80 + 64 KiB
 using Split128x256A12B3 = Split<2, 2, 2, 4, 12, 3>;   // 96 + 48 KiB
 using Split256x256A5B4 = Split<2, 2, 4, 4, 5, 4>;     // 80 + 64 KiB
@@ -802,6 +814,9 @@ const VariantInfo kVariants[] = {
     {"split_128x256_a12b3", true, 256, launch_split<Split128x256A12B3>},
     {"split_256x256_a5b4", true, 256, launch_split<Split256x256A5B4>},
     {"split_128x128_a12b6", true, 128, launch_split<Split128x128A12B6>},
+    {"ring8w_256x256_s4", true, 256, launch_ring<Ring8w256x256S4>},
+    {"ring8w_256x256_s3", true, 256, launch_ring<Ring8w256x256S3>},
+    {"ring8w_128x256_s6", true, 256, launch_ring<Ring8w128x256S6>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -849,6 +864,9 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Ring128x256S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring256x256S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring128x128S8>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w256x256S4>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w256x256S3>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w128x256S6>()) != PIR_OK) return st;
     if ((st = set_split_lds<Split128x256A10B4>()) != PIR_OK) return st;
     if ((st = set_split_lds<Split128x256A12B3>()) != PIR_OK) return st;
     if ((st = set_split_lds<Split256x256A5B4>()) != PIR_OK) return st;

@@ -62,3 +62,34 @@ def test_argument_checks_before_any_device_call(qpir):
     assert lib.pir_hint_update_rows(None, None, 4, None, 4, None, None, 0, None) == 1
     assert lib.pir_workspace_bytes(None, 0) == 0
     assert lib.pir_db_close(None) == 0
+    assert lib.pir_answer_batch_qmajor(None, None, 4, None, None, 0, None) == 1
+    assert lib.pir_client_query(None, 4, 4, None, None, None, 1, None, None) == 1
+    assert lib.pir_client_decode(None, 4, 4, None, None, 1, None, None) == 1
+    assert lib.pir_db_set_variant(None, 0, 0) == 1
+    assert lib.pir_db_get_variant(None, 0) == 0
+    assert lib.pir_server_create(None, None) == 1
+    assert lib.pir_server_destroy(None) == 0
+    assert lib.pir_server_submit(None, 0, None, None, 0, None) == 1
+    assert lib.pir_server_now_ns() > 0
+
+
+def test_variant_tables(qpir):
+    qp = qpir
+    names0 = qp.variant_names(0)
+    names64 = qp.variant_names(64)
+    assert names0[0] == "auto" and names64[0] == "auto"
+    assert len(set(names0)) == len(names0) and len(set(names64)) == len(names64)
+    lib = qp.lib()
+    assert lib.pir_variant_name(64, 999) == b"invalid"
+
+
+def test_server_config_checks(qpir):
+    qp = qpir
+    from paper_2510_03631_amd._lib import ServerConfig
+    lib = qp.lib()
+    out = ctypes.c_void_p()
+    bad = [ServerConfig(0, 1, 1 << 30, 0, 1), ServerConfig(3, 1, 1 << 30, 0, 1),
+           ServerConfig(64, 0, 1 << 30, 0, 1), ServerConfig(64, 17, 1 << 30, 0, 1),
+           ServerConfig(64, 2, 0, 0, 1), ServerConfig(2048, 2, 1 << 30, 0, 1)]
+    for cfg in bad:
+        assert lib.pir_server_create(ctypes.byref(cfg), ctypes.byref(out)) == 2

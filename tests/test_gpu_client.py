@@ -1,0 +1,84 @@
+"""Client-side LWE steps on the GPU against the oracle's client, and the
+full round trip query -> answer -> decode on the device."""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from _util import banner, to_dev_u32, to_dev_u8, to_host_u32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qp(gpu):
+    import paper_2510_03631_amd as p
+    return p
+
+
+def _dev_i32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to("cuda")
+
+
+@pytest.mark.parametrize("R,C,n,B", [(1024, 1024, 1024, 3), (333, 1000, 77, 17),
+                                     (64, 2048, 1500, 1), (2000, 300, 64, 40)])
+def test_client_query_decode_round_trip(qp, R, C, n, B):
+    banner(f"client round trip R={R} C={C} n={n} B={B}")
+    g = workload.rng(R + C + n + B)
+    D = workload.db_bytes(g, R, C)
+    A = workload.uniform_u32(g, (C, n))
+    dr = workload.lwe_draws(g, C, n, B)
+    Ad = to_dev_u32(A)
+    Qt = qp.client_query(Ad, to_dev_u32(dr.s), _dev_i32(dr.e), to_dev_u32(dr.col.astype(np.uint32)))
+    Qt_h = to_host_u32(Qt)
+    for b in range(B):
+        assert np.array_equal(Qt_h[b], oracle.lwe_query(A, dr.s[b], dr.e[b], int(dr.col[b]))), b
+    with qp.Database(to_dev_u8(D)) as db:
+        H = db.setup_hint(Ad)
+        ans = db.answer_batch_qmajor(Qt) if B > 1 else db.answer(Qt[0]).view(1, R)
+        m = qp.client_decode(H, to_dev_u32(dr.s), ans).cpu().numpy()
+        H_h = to_host_u32(H)
+        ans_h = to_host_u32(ans)
+    for b in range(B):
+        assert np.array_equal(m[b], oracle.lwe_decode(ans_h[b], H_h, dr.s[b])), b
+        assert np.array_equal(m[b], D[:, int(dr.col[b])]), b
+
+
+def test_client_decode_boundaries(qp):
+    """Noise at the rounding edges, with H = 0 so the answer is m * 2^24 + noise."""
+    import torch
+    banner("client decode rounding boundaries")
+    m = np.array([0, 7, 255, 0, 100, 255], dtype=np.int64)
+    noise = np.array([(1 << 23) - 1, -(1 << 23), 0, -1, 1 << 23, (1 << 23) - 1])
+    a = (((m << 24) + noise) % (1 << 32)).astype(np.uint32).reshape(1, 6)
+    H = torch.zeros((6, 5), dtype=torch.int32, device="cuda")
+    S = torch.zeros((1, 5), dtype=torch.int32, device="cuda")
+    out = qp.client_decode(H, S, to_dev_u32(a)).cpu().numpy()[0]
+    assert out.tolist() == oracle.lwe_decode(a[0], np.zeros((6, 5), np.uint32),
+                                             np.zeros(5, np.uint32)).tolist()
+    assert out.tolist() == [0, 7, 255, 0, 101, 255]
+
+
+def test_client_full_size(qp):
+    """32768 x 1024 public matrix, 4 queries, against the oracle."""
+    banner("client query 32768x1024, B=4")
+    g = workload.rng(workload.SEED_BASE + 1)
+    C, n, B = 32768, 1024, 4
+    A = workload.uniform_u32(g, (C, n))
+    dr = workload.lwe_draws(g, C, n, B)
+    Qt = to_host_u32(qp.client_query(to_dev_u32(A), to_dev_u32(dr.s), _dev_i32(dr.e),
+                                     to_dev_u32(dr.col.astype(np.uint32))))
+    for b in range(B):
+        assert np.array_equal(Qt[b], oracle.lwe_query(A, dr.s[b], dr.e[b], int(dr.col[b])))
+
+
+def test_client_errors(qp):
+    banner("client argument errors")
+    lib = qp.lib()
+    assert lib.pir_client_query(None, 4, 4, None, None, None, 1, None, None) == 1
+    import torch
+    t = torch.zeros(16, dtype=torch.int32, device="cuda")
+    p = t.data_ptr()
+    assert lib.pir_client_query(p, 0, 4, p, p, p, 1, p, None) == 2
+    assert lib.pir_client_decode(p, 4, 4, p, p, 0, p, None) == 2
