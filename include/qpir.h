@@ -213,6 +213,25 @@ pir_status pir_client_decode(const uint32_t* d_H, uint32_t R, uint32_t n, const 
                              pir_stream_t stream);
 
 /*
+ * Chor XOR PIR response (the ENS instantiation, Section 5.1; the server step
+ * of Algorithm 3), for B queries:
+ *     out[b] = XOR of the rows i of DB whose bit i is set in query b.
+ *
+ *   d_DB    rows x words 32-bit words (a row is one b-bit block), row i at
+ *           d_DB + i * row_pitch_words.  16-byte alignment with words and
+ *           row_pitch_words multiples of 4 enables the vector path.
+ *   d_Q     B x ceil(rows / 32) words: query b packed 32 rows per word,
+ *           bit j of word k selecting row 32k + j; bits past the last row
+ *           are ignored.
+ *   d_out   B x words (cleared and written by the call).
+ *   B == 0 is a no-op.  Errors: PIR_ERR_INVALID_ARG, PIR_ERR_SHAPE,
+ *   PIR_ERR_UNSUPPORTED.
+ */
+pir_status pir_chor_answer(const uint32_t* d_DB, uint32_t rows, uint32_t words,
+                           uint64_t row_pitch_words, const uint32_t* d_Q, uint32_t B,
+                           uint32_t* d_out, pir_stream_t stream);
+
+/*
  * Kernel variants (tile shapes, pipeline depths, rows per wave) for the
  * autotuner.  `batch` == 0 names the single-query path, `batch` >= 1 the
  * batched path.  Variant 0 is the library's built-in choice.  Every variant

@@ -20,6 +20,9 @@ Contents
   interval, Section 4.2), as plain array assignment.
 * ``freivalds``: a randomized whole-matrix check of a claimed product over
   Z/2^32, for shapes too large to recompute.
+* ``chor_*``: Chor XOR PIR (the ENS instantiation, Section 5.1, and the
+  server step of Algorithm 3): XOR of the selected rows, query packing, and
+  the client's reconstruction; ``brute_chor`` with Python integers.
 
 Parity is pinned for every function here (see ``tests/test_oracle_pins.py``):
 brute force on tiny inputs, closed forms, a hand-worked example, the LWE
@@ -224,3 +227,57 @@ def freivalds(D: np.ndarray, Q, out, trials: int = 16, seed: int = 0) -> bool:
         if not np.array_equal(lhs, rhs):
             return False
     return True
+
+
+# --------------------------------------------------------------------------
+# Chor XOR PIR (the ENS instantiation, Section 5.1; server step of
+# Algorithm 3): the response to a query bit vector q is the XOR of the
+# database rows whose bit is set.  Rows are b-bit blocks stored as W 32-bit
+# words; a query over r rows is packed little-endian into ceil(r/32) words
+# (bit j of word k selects row 32k + j).
+# --------------------------------------------------------------------------
+def chor_unpack(qwords, rows: int) -> np.ndarray:
+    """Packed query words -> boolean selector of length ``rows``."""
+    w = np.asarray(qwords, dtype=np.uint32)
+    bits = (w[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1
+    return bits.reshape(-1)[:rows].astype(bool)
+
+
+def chor_pack(sel) -> np.ndarray:
+    sel = np.asarray(sel, dtype=bool)
+    n = (sel.size + 31) // 32
+    padded = np.zeros(n * 32, dtype=np.uint32)
+    padded[:sel.size] = sel
+    return (padded.reshape(n, 32) << np.arange(32, dtype=np.uint32)).sum(axis=1).astype(np.uint32)
+
+
+def chor_answer(DBw: np.ndarray, qwords) -> np.ndarray:
+    """XOR of the rows of ``DBw`` (r x W words) selected by the packed query."""
+    DBw = np.asarray(DBw, dtype=np.uint32)
+    sel = chor_unpack(qwords, DBw.shape[0])
+    if not sel.any():
+        return np.zeros(DBw.shape[1], dtype=np.uint32)
+    return np.bitwise_xor.reduce(DBw[sel], axis=0)
+
+
+def chor_answer_batch(DBw: np.ndarray, Qwords: np.ndarray) -> np.ndarray:
+    """One response per row of ``Qwords`` (B x ceil(r/32) packed queries)."""
+    return np.stack([chor_answer(DBw, q) for q in np.asarray(Qwords, dtype=np.uint32)])
+
+
+def chor_reconstruct(responses) -> np.ndarray:
+    """The client's block: XOR of the servers' responses (Definition 1's
+    BlockReconst for Chor PIR)."""
+    out = np.zeros_like(np.asarray(responses[0], dtype=np.uint32))
+    for r in responses:
+        out ^= np.asarray(r, dtype=np.uint32)
+    return out
+
+
+def brute_chor(rows_bits: list, qbits: list) -> int:
+    """Python-integer brute force: rows as b-bit integers, XOR of selected."""
+    acc = 0
+    for row, bit in zip(rows_bits, qbits):
+        if bit:
+            acc ^= row
+    return acc

@@ -7,7 +7,7 @@ offline hint ``H = D A``, as hand-written HIP kernels behind the C ABI in
 computes on the host.
 """
 from ._lib import (Database, PirError, lib, LIB_PATH, SIGNATURES,  # noqa: F401
-                   client_decode, client_query, variant_names)
+                   chor_answer, client_decode, client_query, variant_names)
 
 __all__ = ["Database", "PirError", "lib", "LIB_PATH", "SIGNATURES", "client_query",
-           "client_decode", "variant_names"]
+           "client_decode", "variant_names", "chor_answer"]

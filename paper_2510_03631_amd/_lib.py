@@ -79,6 +79,7 @@ SIGNATURES = {
     "pir_server_destroy": (_ST, [_P]),
     "pir_client_query": (_ST, [_P, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
     "pir_client_decode": (_ST, [_P, _U32, _U32, _P, _P, _U32, _P, _P]),
+    "pir_chor_answer": (_ST, [_P, _U32, _U32, _U64, _P, _U32, _P, _P]),
 }
 
 
@@ -354,4 +355,26 @@ def client_decode(H: torch.Tensor, S: torch.Tensor, answers: torch.Tensor,
     with torch.cuda.device(dev):
         check(lib().pir_client_decode(hp, R, n, sp, ap, B, op, _stream_ptr(stream, dev)),
               "pir_client_decode")
+    return out
+
+
+def chor_answer(DB: torch.Tensor, Q: torch.Tensor, out: torch.Tensor = None,
+                stream=None) -> torch.Tensor:
+    """Chor XOR-PIR responses: ``DB`` is rows x W words (row stride may be
+    padded), ``Q`` is B x ceil(rows/32) packed selector words; returns B x W."""
+    if DB.dim() != 2 or DB.stride(1) != 1 or DB.dtype not in _WORD:
+        raise ValueError("DB must be a 2-D 32-bit word tensor with unit column stride")
+    rows, W = int(DB.shape[0]), int(DB.shape[1])
+    dev = DB.device
+    if not DB.is_cuda:
+        raise ValueError("DB must be on the GPU")
+    B = int(Q.shape[0])
+    qp_ = _ptr_words(Q, "Q", (B, (rows + 31) // 32), dev)
+    if out is None:
+        out = torch.empty((B, W), dtype=torch.int32, device=dev)
+    op = _ptr_words(out, "out", (B, W), dev)
+    pitch = int(DB.stride(0)) if rows > 1 else W
+    with torch.cuda.device(dev):
+        check(lib().pir_chor_answer(DB.data_ptr(), rows, W, pitch, qp_, B, op,
+                                    _stream_ptr(stream, dev)), "pir_chor_answer")
     return out

@@ -71,6 +71,8 @@ def test_argument_checks_before_any_device_call(qpir):
     assert lib.pir_server_destroy(None) == 0
     assert lib.pir_server_submit(None, 0, None, None, 0, None) == 1
     assert lib.pir_server_now_ns() > 0
+    assert lib.pir_chor_answer(None, 4, 4, 4, None, 1, None, None) == 1
+    assert lib.pir_chor_answer(None, 4, 4, 4, None, 0, None, None) == 0
 
 
 def test_variant_tables(qpir):

@@ -222,3 +222,61 @@ def test_decode_rounding_boundaries():
     a = ((m << 24) + noise) % M32
     dec = oracle.lwe_decode(a.astype(np.uint32), H, s)
     assert dec.tolist() == [0, 7, 255, 0, 101, 255]
+
+
+# ---------------------------------------------------------------- Chor XOR PIR
+def test_chor_handworked():
+    # rows 0b0011, 0b0101, 0b1001 as one-word blocks; select rows 0 and 2:
+    # 0011 ^ 1001 = 1010
+    DB = np.array([[3], [5], [9]], dtype=np.uint32)
+    assert oracle.chor_answer(DB, [0b101]).tolist() == [0b1010]
+    assert oracle.chor_answer(DB, [0b111]).tolist() == [3 ^ 5 ^ 9]
+    assert oracle.chor_answer(DB, [0]).tolist() == [0]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_chor_brute_force(seed):
+    g = np.random.default_rng(seed)
+    r, W = int(g.integers(1, 70)), int(g.integers(1, 5))
+    DB = g.integers(0, M32, size=(r, W), dtype=np.uint32)
+    q = workload.chor_query_words(g, r, 1)[0]
+    sel = oracle.chor_unpack(q, r)
+    rows_int = [sum(int(DB[i, w]) << (32 * w) for w in range(W)) for i in range(r)]
+    got = oracle.chor_answer(DB, q)
+    got_int = sum(int(got[w]) << (32 * w) for w in range(W))
+    assert got_int == oracle.brute_chor(rows_int, sel.tolist())
+    # packing round trip, and the last word's padding bits stay zero
+    assert np.array_equal(oracle.chor_pack(sel), q)
+
+
+def test_chor_closed_forms_and_linearity():
+    g = np.random.default_rng(3)
+    r, W = 100, 7
+    DB = g.integers(0, M32, size=(r, W), dtype=np.uint32)
+    for i in (0, 31, 32, 99):
+        e = np.zeros(r, dtype=bool)
+        e[i] = True
+        assert np.array_equal(oracle.chor_answer(DB, oracle.chor_pack(e)), DB[i])
+    allq = oracle.chor_pack(np.ones(r, dtype=bool))
+    assert np.array_equal(oracle.chor_answer(DB, allq), np.bitwise_xor.reduce(DB, axis=0))
+    q1, q2 = workload.chor_query_words(g, r, 2)
+    assert np.array_equal(oracle.chor_answer(DB, q1 ^ q2),
+                          oracle.chor_answer(DB, q1) ^ oracle.chor_answer(DB, q2))
+
+
+@pytest.mark.parametrize("servers", [2, 3, 5])
+def test_chor_reconstruction(servers):
+    """Shares that XOR to the unit vector of theta: the XOR of the servers'
+    responses is row theta (Chor's correctness, Section 5.1)."""
+    g = np.random.default_rng(servers)
+    r, W, theta = 77, 6, 41
+    DB = g.integers(0, M32, size=(r, W), dtype=np.uint32)
+    shares = list(workload.chor_shares(g, r, theta, servers))
+    e = np.zeros(r, dtype=bool)
+    e[theta] = True
+    last = oracle.chor_pack(e)
+    for s in shares:
+        last = last ^ s
+    shares.append(last)
+    resp = [oracle.chor_answer(DB, s) for s in shares]
+    assert np.array_equal(oracle.chor_reconstruct(resp), DB[theta])

@@ -167,3 +167,28 @@ def device_u32(shape, seed: int, device="cuda"):
     t.random_(0, 1 << 32, generator=gen)
     t = torch.where(t >= (1 << 31), t - (1 << 32), t)
     return t.to(torch.int32)
+
+
+# Chor XOR PIR workloads (the ENS instantiation's measurements: databases of
+# 2^12 .. 2^18 entries of 3 KB each, batches of 1, 2^7 and 2^10 queries).
+CHOR_ENTRY_BYTES = 3072
+CHOR_ROWS = (1 << 12, 1 << 14, 1 << 16, 1 << 18)
+CHOR_BATCHES = (1, 1 << 7, 1 << 10)
+
+
+def chor_query_words(g: np.random.Generator, rows: int, batch: int) -> np.ndarray:
+    """Uniformly random selector bits, packed 32 per word (batch x ceil(rows/32));
+    bits past ``rows`` are zero."""
+    nw = (rows + 31) // 32
+    q = uniform_u32(g, (batch, nw))
+    tail = rows - 32 * (nw - 1)
+    if tail < 32:
+        q[:, -1] &= np.uint32((1 << tail) - 1)
+    return q
+
+
+def chor_shares(g: np.random.Generator, rows: int, theta: int, servers: int) -> np.ndarray:
+    """Random draws of a Chor client: ``servers - 1`` uniform selector words
+    per server (the last server's share is fixed by the client from these
+    and theta).  Returns (servers - 1) x ceil(rows/32) words."""
+    return chor_query_words(g, rows, servers - 1)
