@@ -166,6 +166,40 @@ def large_bench(stream) -> dict:
     return res
 
 
+def chor_bench(stream) -> dict:
+    """Chor XOR PIR (the ENS instantiation) at the paper's largest database:
+    2^18 entries of 3 KB (768 MiB), batches of 1, 2^7 and 2^10 random
+    queries.  The paper's Table 2 reports 15.42 / 154.74 / 1269.30 ms for its
+    GPU rows at this size (on another GPU, including fixed overheads); they
+    are context, not a target."""
+    import numpy as np
+    import torch
+    import paper_2510_03631_amd as qp
+    import workload
+    dev = torch.device("cuda:0")
+    rows, W = 1 << 18, workload.CHOR_ENTRY_BYTES // 4
+    DB = workload.device_u32((rows, W), workload.SEED_BASE + 60, dev)
+    res = {"workload": f"{rows} entries x {workload.CHOR_ENTRY_BYTES} B "
+                       f"({rows * W * 4 / 2**20:.0f} MiB), random selector bits",
+           "paper_table2_gpu_ms": {"1": 15.42, "128": 154.74, "1024": 1269.30}}
+    g = workload.rng(workload.SEED_BASE + 62)
+    for B in workload.CHOR_BATCHES:
+        Q = torch.from_numpy(workload.chor_query_words(g, rows, B).view(np.int32)).to(dev)
+        out = torch.empty((B, W), dtype=torch.int32, device=dev)
+        fn = lambda: qp.chor_answer(DB, Q, out=out)
+        fn()
+        reps = 10 if B < 1024 else 3
+        _, ev = time_on_stream(fn, reps, stream)
+        t = ev / reps
+        res[f"B{B}"] = {"ms": round(t * 1e3, 4),
+                        "db_gbs": round(rows * W * 4 / t / 1e9, 1),
+                        "queries_per_s": round(B / t, 1),
+                        "xor_gbs": round(B * rows * W * 4 / 2 / t / 1e9, 1)}
+    del DB
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_run(srv, t_off, which, qs) -> dict:
     """Replay one open-loop trace; latency percentiles and throughput."""
     import numpy as np
@@ -306,6 +340,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-chor", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--profile", choices=["answer", "batch", "hint", "calibrate"],
                     help="run only one kernel family (for rocprofv3 runs) and exit")
@@ -419,6 +454,13 @@ def main() -> int:
         del D
         torch.cuda.empty_cache()
         result["large_b256"] = large_bench(stream)
+
+    if not args.no_chor:
+        log("chor XOR PIR: 2^18 x 3 KB, batches 1 / 128 / 1024")
+        if db._h is not None:
+            db.close()
+        torch.cuda.empty_cache()
+        result["chor"] = chor_bench(stream)
 
     if not args.no_serving:
         log("serving: 8 resident databases, Poisson arrivals, Zipf(1.1)")
