@@ -291,20 +291,23 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
 
-template <int WM_, int WN_, int TM_, int TN_, int STAGES_>
+template <int WM_, int WN_, int TM_, int TN_, int STAGES_, int BK_ = 64>
 struct Ring {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, STAGES = STAGES_;
     static constexpr int NW = WM * WN;                   // waves per workgroup
     static constexpr int THREADS = 64 * NW;
-    static constexpr int BK = 64;
+    static constexpr int BK = BK_;                       // k bytes per stage: 64 or 128
+    static constexpr int SEGS = BK / 16;                 // 16-byte slots per LDS row
+    static constexpr int RPB = 1024 / BK;                // rows per 1 KiB block
     static constexpr int BM = WM * TM * 32;
     static constexpr int BN = WN * TN * 32;
     static constexpr int A_BYTES = BM * BK;
     static constexpr int STAGE_BYTES = (BM + BN) * BK;
-    static constexpr int A_BLOCKS = BM / 16;             // 1 KiB blocks of 16 rows
-    static constexpr int BLOCKS = (BM + BN) / 16;
+    static constexpr int A_BLOCKS = BM / RPB;            // 1 KiB blocks
+    static constexpr int BLOCKS = (BM + BN) / RPB;
     static constexpr int LOADS = BLOCKS / NW;            // per wave per tile
     static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
+    static_assert(BK == 64 || BK == 128, "64- or 128-byte stages");
     static_assert(NW == 4 || NW == 8, "four or eight waves");
     static_assert(TN % 4 == 0, "a wave covers whole groups of four limbs");
     static_assert(BLOCKS % NW == 0, "blocks split evenly over waves");
@@ -312,7 +315,14 @@ struct Ring {
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
-__device__ inline int slot_of(int row, int seg) { return seg ^ ((row >> 1) & 3); }
+// 16-byte slot of (row, segment) in an LDS row: an XOR swizzle so that the
+// fragment reads (32 consecutive rows, one segment) hit distinct banks.
+template <int BK>
+__device__ inline int swz(int row, int seg) {
+    return BK == 64 ? (seg ^ ((row >> 1) & 3)) : (seg ^ (row & 7));
+}
+
+__device__ inline int slot_of(int row, int seg) { return swz<64>(row, seg); }
 
 // s_waitcnt with only vmcnt constrained (gfx9 encoding: vmcnt low bits
 // [3:0], high bits [15:14]; expcnt and lgkmcnt left at their maximum).
@@ -368,8 +378,9 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     const uint32_t m0 = tile_m * T::BM;
     const uint32_t n0 = tile_n * T::BN;
 
-    // Per-lane source of each of this wave's LOADS block loads.
-    const int lrow = lane >> 2;                           // row within a 1 KiB block
+    // Per-lane source of each of this wave's LOADS block loads: lane l of a
+    // load fills slot l % SEGS of row l / SEGS of a 1 KiB block.
+    const int lrow = lane / T::SEGS;                      // row within a 1 KiB block
     const uint8_t* src[T::LOADS];
     uint32_t seg_off[T::LOADS];
     bool is_a[T::LOADS];
@@ -377,8 +388,8 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     for (int i = 0; i < T::LOADS; ++i) {
         const int kb = wave + T::NW * i;
         const bool a = kb < T::A_BLOCKS;
-        const int r = (a ? kb : kb - T::A_BLOCKS) * 16 + lrow;
-        const int seg = (lane & 3) ^ ((r >> 1) & 3);
+        const int r = (a ? kb : kb - T::A_BLOCKS) * T::RPB + lrow;
+        const int seg = swz<T::BK>(r, lane % T::SEGS);
         is_a[i] = a;
         seg_off[i] = 16u * seg;
         if (a) {
@@ -448,14 +459,14 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
 #pragma unroll
             for (int a = 0; a < T::TM; ++a) {
                 const int r = wm * T::TM * 32 + a * 32 + frow;
-                u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * slot_of(r, seg));
+                u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * swz<T::BK>(r, seg));
                 v ^= centre;
                 fa[buf][a] = __builtin_bit_cast(i32x4, v);
             }
 #pragma unroll
             for (int b = 0; b < T::TN; ++b) {
                 const int r = wn * T::TN * 32 + b * 32 + frow;
-                fb[buf][b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * slot_of(r, seg));
+                fb[buf][b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * swz<T::BK>(r, seg));
             }
         };
         read_frags(0, 0);
@@ -788,6 +799,10 @@ using Ring128x128S8 = Ring<4, 1, 1, 4, 8>;   // 128 KiB
 using Ring8w256x256S4 = Ring<4, 2, 2, 4, 4>;  // 8 waves, 128 KiB
 using Ring8w256x256S3 = Ring<4, 2, 2, 4, 3>;  // 8 waves,  96 KiB
 using Ring8w128x256S6 = Ring<4, 2, 1, 4, 6>;  // 8 waves, 144 KiB
+using Ring8w128x256K128S3 = Ring<4, 2, 1, 4, 3, 128>;  // 8 waves, 144 KiB, 128-byte stages
+using Ring128x256K128S3 = Ring<2, 2, 2, 4, 3, 128>;    // 144 KiB
+using Ring8w256x256K128S2 = Ring<4, 2, 2, 4, 2, 128>;  // 8 waves, 128 KiB
+using Ring128x128K128S4 = Ring<4, 1, 1, 4, 4, 128>;    // 128 KiB
 using Split128x256A10B4 = Split<2, 2, 2, 4, 10, 4>;   // 80 + 64 KiB
 using Split128x256A12B3 = Split<2, 2, 2, 4, 12, 3>;   // 96 + 48 KiB
 using Split256x256A5B4 = Split<2, 2, 4, 4, 5, 4>;     // 80 + 64 KiB
@@ -817,6 +832,10 @@ const VariantInfo kVariants[] = {
     {"ring8w_256x256_s4", true, 256, launch_ring<Ring8w256x256S4>},
     {"ring8w_256x256_s3", true, 256, launch_ring<Ring8w256x256S3>},
     {"ring8w_128x256_s6", true, 256, launch_ring<Ring8w128x256S6>},
+    {"ring8w_128x256_k128_s3", true, 256, launch_ring<Ring8w128x256K128S3>},
+    {"ring_128x256_k128_s3", true, 256, launch_ring<Ring128x256K128S3>},
+    {"ring8w_256x256_k128_s2", true, 256, launch_ring<Ring8w256x256K128S2>},
+    {"ring_128x128_k128_s4", true, 128, launch_ring<Ring128x128K128S4>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -867,6 +886,10 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Ring8w256x256S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring8w256x256S3>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring8w128x256S6>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w128x256K128S3>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring128x256K128S3>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w256x256K128S2>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring128x128K128S4>()) != PIR_OK) return st;
     if ((st = set_split_lds<Split128x256A10B4>()) != PIR_OK) return st;
     if ((st = set_split_lds<Split128x256A12B3>()) != PIR_OK) return st;
     if ((st = set_split_lds<Split256x256A5B4>()) != PIR_OK) return st;

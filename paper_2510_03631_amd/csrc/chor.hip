@@ -12,12 +12,13 @@
 // * a workgroup (256 threads) owns a slab of rows, a group of up to G = 16
 //   queries and a 1024-word column chunk: lane t holds words 4t..4t+3 of the
 //   chunk for every query of the group (G x 16-byte accumulators);
-// * per 32-row block the group's 32 query bits per query are loaded once
-//   (wave-uniform); a row that no query of the group selects is never read;
-//   the selected rows of 8 consecutive rows are loaded back to back (up to
-//   8 KiB per wave in flight), then XORed into the accumulators of the
-//   queries that select them, with wave-uniform branches (only selected
-//   (row, query) pairs cost VALU work);
+// * per 32-row block the group's selector words are loaded once (lane g
+//   holds query g's word; wave-uniform reads pick bits out), and rows are
+//   loaded 8 at a time, back to back;
+// * batches of at most 4 queries XOR every row under a wave-uniform mask;
+//   larger batches build, per 4 rows, the 16 XOR combinations of the rows
+//   in a wave-private LDS table and add one table entry per query (method
+//   of the Four Russians): one LDS read and XOR per query per 4 rows;
 // * workgroups are numbered slab-major and dealt to XCDs in contiguous
 //   ranges, so the query groups of one slab share its rows in L2;
 // * slabs combine into the output with atomicXor (XOR is associative and
@@ -29,7 +30,6 @@
 
 namespace {
 
-constexpr int kG = 16;            // queries per workgroup
 constexpr int kThreads = 256;
 constexpr uint32_t kChunkWords = 4 * kThreads;
 
@@ -45,12 +45,26 @@ __device__ inline u32x4 load_words(const uint32_t* row, uint32_t w, uint32_t W) 
                  w + 2 < W ? row[w + 2] : 0u, w + 3 < W ? row[w + 3] : 0u};
 }
 
-template <bool VEC>
+// Work of one workgroup: rows [r0, r1) of a slab, queries [b0, b0 + nb) of a
+// group, all columns in chunks of 1024 words (lane t: words 4t..4t+3).
+//
+// TABLE == false (batches of at most 4): every row is streamed and XORed
+// under a wave-uniform mask, acc_g ^= row & -(bit), no branches.
+// TABLE == true: for every 4 consecutive rows the wave writes the 16 XOR
+// combinations of its slice into a private LDS table (method of the Four
+// Russians); each query then costs one LDS read at the index given by its
+// 4 selector bits and one XOR, instead of a test and XOR per row.
+template <int G, bool TABLE, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ DB, uint64_t pitch,
                                                    uint32_t rows, uint32_t W,
                                                    const uint32_t* __restrict__ Q, uint32_t qwords,
                                                    uint32_t B, uint32_t slab_rows,
                                                    uint32_t n_groups, uint32_t* __restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) u32x4 s_table[];   // [wave][16][64]
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u32x4* tab = s_table + wave * 16 * 64;
+
     uint32_t bid = blockIdx.x;
     {
         const uint32_t per = gridDim.x / 8u;
@@ -60,50 +74,85 @@ __global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ 
     const uint32_t grp = bid % n_groups;
     const uint32_t r0 = slab * slab_rows;
     const uint32_t r1 = min(rows, r0 + slab_rows);
-    const uint32_t b0 = grp * kG;
-    const uint32_t nb = min((uint32_t)kG, B - b0);
+    const uint32_t b0 = grp * G;
+    const uint32_t nb = min((uint32_t)G, B - b0);
+    if (TABLE) tab[lane] = u32x4{0, 0, 0, 0};   // entry 0: no row selected
 
     for (uint32_t c0 = 0; c0 < W; c0 += kChunkWords) {
         const uint32_t w = c0 + 4u * threadIdx.x;
         const bool active = w < W;
-        u32x4 acc[kG];
+        u32x4 acc[G];
 #pragma unroll
-        for (int g = 0; g < kG; ++g) acc[g] = u32x4{0, 0, 0, 0};
+        for (int g = 0; g < G; ++g) acc[g] = u32x4{0, 0, 0, 0};
 
         for (uint32_t r = r0; r < r1; r += 32) {
-            // This block's selector bits for each query of the group.
-            uint32_t qb[kG];
-            uint32_t any = 0;
-            const uint32_t valid = (r1 - r >= 32) ? 0xFFFFFFFFu : ((1u << (r1 - r)) - 1u);
-#pragma unroll
-            for (int g = 0; g < kG; ++g) {
-                qb[g] = (uint32_t)g < nb
-                            ? __builtin_amdgcn_readfirstlane(Q[(uint64_t)(b0 + g) * qwords + r / 32]) & valid
-                            : 0u;
-                any |= qb[g];
-            }
-            if (!any) continue;
-#pragma unroll
-            for (int j0 = 0; j0 < 32; j0 += 8) {
-                if (!((any >> j0) & 0xFFu)) continue;
+            const uint32_t nrow = min(32u, r1 - r);
+            const uint32_t valid = nrow == 32 ? 0xFFFFFFFFu : ((1u << nrow) - 1u);
+            // Lane g < nb holds query g's 32 selector bits for this block.
+            const uint32_t qv = (uint32_t)lane < nb ? (Q[(uint64_t)(b0 + lane) * qwords + r / 32] & valid)
+                                                    : 0u;
+#pragma unroll 1
+            for (int s8 = 0; s8 < 32; s8 += 8) {
                 u32x4 d[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     d[k] = u32x4{0, 0, 0, 0};
-                    if (((any >> (j0 + k)) & 1u) && active)
-                        d[k] = load_words<VEC>(DB + (uint64_t)(r + j0 + k) * pitch, w, W);
+                    if ((uint32_t)(s8 + k) < nrow && active)
+                        d[k] = load_words<VEC>(DB + (uint64_t)(r + s8 + k) * pitch, w, W);
                 }
+                if (!TABLE) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
+                    for (int g = 0; g < G; ++g) {
+                        const uint32_t q = __builtin_amdgcn_readlane(qv, g);
 #pragma unroll
-                    for (int g = 0; g < kG; ++g)
-                        if ((qb[g] >> (j0 + k)) & 1u) acc[g] ^= d[k];
+                        for (int k = 0; k < 8; ++k) {
+                            const uint32_t m = 0u - ((q >> (s8 + k)) & 1u);
+                            acc[g] ^= d[k] & u32x4{m, m, m, m};
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const u32x4 x0 = d[4 * h], x1 = d[4 * h + 1], x2 = d[4 * h + 2],
+                                    x3 = d[4 * h + 3];
+                        const u32x4 t3 = x0 ^ x1, t5 = x2 ^ x0, t6 = x2 ^ x1, t7 = x2 ^ t3;
+                        // Entries 1..15 (entry i XORs the rows whose bit is set in i).
+                        tab[1 * 64 + lane] = x0;
+                        tab[2 * 64 + lane] = x1;
+                        tab[3 * 64 + lane] = t3;
+                        tab[4 * 64 + lane] = x2;
+                        tab[5 * 64 + lane] = t5;
+                        tab[6 * 64 + lane] = t6;
+                        tab[7 * 64 + lane] = t7;
+                        tab[8 * 64 + lane] = x3;
+                        tab[9 * 64 + lane] = x3 ^ x0;
+                        tab[10 * 64 + lane] = x3 ^ x1;
+                        tab[11 * 64 + lane] = x3 ^ t3;
+                        tab[12 * 64 + lane] = x3 ^ x2;
+                        tab[13 * 64 + lane] = x3 ^ t5;
+                        tab[14 * 64 + lane] = x3 ^ t6;
+                        tab[15 * 64 + lane] = x3 ^ t7;
+                        // The table is private to the wave and LDS accesses of a
+                        // wave complete in order; keep the compiler from moving
+                        // the reads above the writes.
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        const int sh = s8 + 4 * h;
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            const uint32_t idx = (__builtin_amdgcn_readlane(qv, g) >> sh) & 15u;
+                            acc[g] ^= tab[idx * 64 + lane];
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
                 }
+                if ((uint32_t)(s8 + 8) >= nrow) break;
             }
         }
         if (active) {
 #pragma unroll
-            for (int g = 0; g < kG; ++g) {
+            for (int g = 0; g < G; ++g) {
                 if ((uint32_t)g >= nb) break;
                 uint32_t* o = out + (uint64_t)(b0 + g) * W + w;
                 const uint32_t v[4] = {acc[g].x, acc[g].y, acc[g].z, acc[g].w};
@@ -113,6 +162,30 @@ __global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ 
             }
         }
     }
+}
+
+template <int G, bool TABLE>
+pir_status launch_chor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
+                       const uint32_t* d_Q, uint32_t B, uint32_t* d_out, uint32_t target_blocks,
+                       hipStream_t s) {
+    const uint32_t qwords = (rows + 31) / 32;
+    const uint32_t n_groups = (B + G - 1) / G;
+    uint64_t slab = ((uint64_t)rows * n_groups + target_blocks - 1) / target_blocks;
+    slab = (slab + 31) / 32 * 32;
+    if (slab < 32) slab = 32;
+    const uint64_t n_slabs = (rows + slab - 1) / slab;
+    const uint64_t blocks = n_slabs * n_groups;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    const size_t lds = TABLE ? (size_t)4 * 16 * 64 * sizeof(u32x4) : 0;
+    const bool vec = ((uintptr_t)d_DB % 16 == 0) && (words % 4 == 0) && (pitch % 4 == 0);
+    if (vec)
+        k_chor<G, TABLE, true><<<(uint32_t)blocks, kThreads, lds, s>>>(
+            d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_groups, d_out);
+    else
+        k_chor<G, TABLE, false><<<(uint32_t)blocks, kThreads, lds, s>>>(
+            d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_groups, d_out);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
 }
 
 bool current_is_gfx950() {
@@ -140,26 +213,12 @@ pir_status pir_chor_answer(const uint32_t* d_DB, uint32_t rows, uint32_t words,
     const uint64_t n_out = (uint64_t)B * words;
     k_chor_zero<<<(uint32_t)((n_out + 255) / 256), 256, 0, s>>>(d_out, n_out);
     PIR_LAUNCH_CHECK();
-    const uint32_t qwords = (rows + 31) / 32;
-    const uint32_t n_groups = (B + kG - 1) / kG;
-    // About 2048 workgroups: slabs of a multiple of 32 rows.
-    uint64_t slab = ((uint64_t)rows * n_groups + 2047) / 2048;
-    slab = (slab + 31) / 32 * 32;
-    if (slab < 32) slab = 32;
-    const uint64_t n_slabs = (rows + slab - 1) / slab;
-    const uint64_t blocks = n_slabs * n_groups;
-    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
-    const bool vec = ((uintptr_t)d_DB % 16 == 0) && (words % 4 == 0) && (row_pitch_words % 4 == 0);
-    if (vec)
-        k_chor<true><<<(uint32_t)blocks, kThreads, 0, s>>>(d_DB, row_pitch_words, rows, words, d_Q,
-                                                           qwords, B, (uint32_t)slab, n_groups,
-                                                           d_out);
-    else
-        k_chor<false><<<(uint32_t)blocks, kThreads, 0, s>>>(d_DB, row_pitch_words, rows, words, d_Q,
-                                                            qwords, B, (uint32_t)slab, n_groups,
-                                                            d_out);
-    PIR_LAUNCH_CHECK();
-    return PIR_OK;
+    // Small batches stream every row under masks; larger ones use the
+    // 4-row tables.  Fewer, longer slabs for large batches keep the number of
+    // output atomics down.
+    if (B <= 4) return launch_chor<4, false>(d_DB, rows, words, row_pitch_words, d_Q, B, d_out, 2048, s);
+    if (B <= 64) return launch_chor<16, true>(d_DB, rows, words, row_pitch_words, d_Q, B, d_out, 2048, s);
+    return launch_chor<32, true>(d_DB, rows, words, row_pitch_words, d_Q, B, d_out, 512, s);
 }
 
 }  // extern "C"
