@@ -315,11 +315,17 @@ struct Ring {
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
-// 16-byte slot of (row, segment) in an LDS row: an XOR swizzle so that the
-// fragment reads (32 consecutive rows, one segment) hit distinct banks.
+// 16-byte slot of (row, segment) in an LDS row.  A fragment read has 32
+// lanes on 32 consecutive rows at one segment; gfx950's LDS serves a
+// 16-byte read 16 lanes at a time across 64 four-byte banks, so the 16 rows
+// of a pass must land on 16 distinct 16-byte bank groups.  A 64-byte row
+// spans 16 banks (row % 4 picks the quarter of the bank space), a 128-byte
+// row 32 banks (row % 2); XORing the segment with the next row bits fills
+// the remaining choices.  (Measured: the earlier swizzle, conflict-free for
+// 8 lanes over 32 banks, spent half of the LDS cycles in bank conflicts.)
 template <int BK>
 __device__ inline int swz(int row, int seg) {
-    return BK == 64 ? (seg ^ ((row >> 1) & 3)) : (seg ^ (row & 7));
+    return BK == 64 ? (seg ^ ((row >> 2) & 3)) : (seg ^ ((row >> 1) & 7));
 }
 
 __device__ inline int slot_of(int row, int seg) { return swz<64>(row, seg); }
@@ -575,7 +581,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ 
     for (int i = 0; i < NL; ++i) {
         const int kb = lw + 2 * i;                         // 1 KiB block within the tile
         const int r = kb * 16 + lrow;
-        const int seg = (lane & 3) ^ ((r >> 1) & 3);
+        const int seg = swz<64>(r, lane & 3);
         seg_off[i] = 16u * seg;
         if (loads_d) {
             uint32_t mi = m0 + (uint32_t)min(r, T::BM - 1);
