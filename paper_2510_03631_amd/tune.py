@@ -111,8 +111,9 @@ def main(argv=None) -> int:
         with Database(D) as db:
             res = tune_database(db, batches, args.reps,
                                 log=lambda m: print(m, flush=True))
-        table[f"{R}x{C}"] = {"best": best(res),
-                             "us": {str(B): t for B, t in res.items()}}
+        entry = table.setdefault(f"{R}x{C}", {"best": {}, "us": {}})
+        entry["best"].update(best(res))          # merge: other batch sizes keep their choice
+        entry["us"].update({str(B): t for B, t in res.items()})
         del D
         torch.cuda.empty_cache()
     with open(args.out, "w") as f:
