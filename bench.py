@@ -6,8 +6,11 @@ uint8 database (1 GiB) with one LWE query (n = 1024, sigma = 6.4).  A step is
 one Answer over the resident database; inputs are in HBM before timing.
 
 Also reported on the same line: the 64-query batched Answer and the offline
-hint on the same database (matrix cores), and the oracle timed on the host
-cores on a bounded sample (``cpu_baseline``).
+hint on the same database (matrix cores); a 16 GiB database (256-query batch,
+hint, 1% refresh with incremental hint); Chor XOR PIR and the Goldberg field
+form at 2^18 records of 3 KB; the serving loop (latency percentiles under
+Poisson arrivals); and the oracle timed on the host cores on a bounded sample
+(``cpu_baseline``).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -200,6 +203,43 @@ def chor_bench(stream) -> dict:
     return res
 
 
+def ftr_bench(stream) -> dict:
+    """Goldberg IT-PIR (the FTR instantiation): the server product D Q mod p
+    over the paper's largest database, 2^18 records of 3 KB stored as a
+    3072 x 262144 byte matrix (one column per record), for share batches of
+    1, 2^7 and 2^10 queries.  The paper's Table 2 reports 840.70 / 1720.35 /
+    9672.28 ms for its GPU rows at this size (on another GPU, including fixed
+    overheads); context, not a target."""
+    import torch
+    import paper_2510_03631_amd as qp
+    import workload
+    dev = torch.device("cuda:0")
+    R, C, p = workload.FTR_RECORD_BYTES, workload.FTR_RECORDS[-1], workload.FTR_PRIME
+    D = workload.device_db(R, C, workload.SEED_BASE + 70, dev)
+    db = qp.Database(D)
+    res = {"workload": f"{C} records x {R} B ({R * C / 2**20:.0f} MiB) as {R} x {C} bytes, "
+                       f"share words mod p = {p}",
+           "paper_table2_gpu_ms": {"1": 840.70, "128": 1720.35, "1024": 9672.28}}
+    for B in workload.FTR_BATCHES:
+        Q = workload.device_mod((C, B), p, workload.SEED_BASE + 71 + B, dev)
+        out = torch.empty((R, B), dtype=torch.int32, device=dev)
+        ws = db.workspace(B)
+        fn = lambda: db.answer_batch_modp(Q, p, out=out, ws=ws)
+        fn()
+        reps = 20 if B < 1024 else 5
+        _, ev = time_on_stream(fn, reps, stream)
+        t = ev / reps
+        res[f"B{B}"] = {"ms": round(t * 1e3, 4),
+                        "db_gbs": round(R * C / t / 1e9, 1),
+                        "queries_per_s": round(B / t, 1),
+                        "mfma_frac": round(8.0 * R * C * B / t / 1e12 / INT8_PEAK_TOPS, 4)}
+        del Q, out
+    db.close()
+    del D
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_run(srv, t_off, which, qs) -> dict:
     """Replay one open-loop trace; latency percentiles and throughput."""
     import numpy as np
@@ -341,6 +381,7 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-chor", action="store_true")
+    ap.add_argument("--no-ftr", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--profile", choices=["answer", "batch", "hint", "calibrate"],
                     help="run only one kernel family (for rocprofv3 runs) and exit")
@@ -461,6 +502,13 @@ def main() -> int:
             db.close()
         torch.cuda.empty_cache()
         result["chor"] = chor_bench(stream)
+
+    if not args.no_ftr:
+        log("goldberg field form: 2^18 x 3 KB, batches 1 / 128 / 1024")
+        if db._h is not None:
+            db.close()
+        torch.cuda.empty_cache()
+        result["ftr"] = ftr_bench(stream)
 
     if not args.no_serving:
         log("serving: 8 resident databases, Poisson arrivals, Zipf(1.1)")

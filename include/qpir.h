@@ -7,6 +7,7 @@
  *   answer      a   = D q        mod 2^32   (D: R x C bytes, q: C words)
  *   batch       Out = D Q        mod 2^32   (Q: C x B words)
  *   hint        H   = D A        mod 2^32   (A: C x n words, offline)
+ *   field       Out = D Q        mod p      (Goldberg shares, p < 2^32)
  *
  * This is the response step of the PIR interface (Definition 1: each
  * database server turns a query into a response derived from its local
@@ -24,7 +25,8 @@
  *   nor retains them after the call returns, except the database bytes that
  *   a handle borrows (see pir_db_open).
  * - Matrices are row-major, elements of 32-bit words are unsigned and all
- *   arithmetic wraps modulo 2^32 (results are exact, bit for bit).
+ *   arithmetic wraps modulo 2^32 (results are exact, bit for bit), except
+ *   pir_answer_batch_modp, which reduces the exact product modulo p.
  * - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
  *   and the call returns without waiting; results are valid once the stream
  *   reaches that point.  Only pir_db_open and pir_db_close synchronize.
@@ -103,7 +105,8 @@ pir_status pir_db_shape(const pir_db_t* db, uint64_t* rows, uint64_t* cols);
 /*
  * Workspace bytes needed by a call on `db`:
  *   batch == 0   pir_answer
- *   batch == B   pir_answer_batch with B queries, pir_setup_hint and
+ *   batch == B   pir_answer_batch, pir_answer_batch_qmajor and
+ *                pir_answer_batch_modp with B queries, pir_setup_hint and
  *                pir_hint_update_rows with n = B.
  * The value may be 0.
  */
@@ -146,6 +149,26 @@ pir_status pir_answer_batch(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint3
 pir_status pir_answer_batch_qmajor(pir_db_t* db, const uint32_t* d_Qt, uint32_t B,
                                    uint32_t* d_outT, void* d_ws, size_t ws_bytes,
                                    pir_stream_t stream);
+
+/*
+ * Batched Answer over a prime field: Out[r][b] = sum_j D[r][j] * Q[j][b]
+ * mod p.  This is the server product of the Goldberg (FTR) instantiation
+ * (Section 5.1; the "mod q" batched product of Algorithm 4): each query
+ * column holds one server's Shamir shares (one field element per database
+ * column), and the client interpolates the servers' responses.  Database
+ * bytes are field elements in [0, 256); query words are taken as integers
+ * (normally residues in [0, p)); the result is exact, reduced once.
+ *
+ *   p      modulus, 2 <= p < 2^32 (prime for Shamir sharing; not checked).
+ *   d_Q    C x B words, row-major.   d_out  R x B words in [0, p), row-major.
+ *   d_ws   workspace of pir_workspace_bytes(db, B) bytes.
+ * Requires a 16-byte aligned database with C a multiple of 16
+ * (PIR_ERR_UNSUPPORTED otherwise) and C <= 2^23 (PIR_ERR_SHAPE).  p < 2
+ * gives PIR_ERR_INVALID_ARG.  B == 0 is a no-op.
+ */
+pir_status pir_answer_batch_modp(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint32_t p,
+                                 uint32_t* d_out, void* d_ws, size_t ws_bytes,
+                                 pir_stream_t stream);
 
 /*
  * Offline hint: H = D A mod 2^32 (the client-independent part of the

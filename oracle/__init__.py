@@ -23,6 +23,15 @@ Contents
 * ``chor_*``: Chor XOR PIR (the ENS instantiation, Section 5.1, and the
   server step of Algorithm 3): XOR of the selected rows, query packing, and
   the client's reconstruction; ``brute_chor`` with Python integers.
+* ``answer_batch_mod`` / ``answer_mod_entries`` / ``brute_answer_batch_mod``:
+  the Goldberg (FTR) server product ``D Q mod p`` (Section 5.1; Algorithm 4's
+  "mod q"), exact sums reduced once (C loops with 128-bit sums; numpy
+  uint64 dot products for sampled entries; Python integers).
+* ``shamir_shares`` / ``lagrange_at_zero``: the client side of Goldberg's
+  IT-PIR as the paper describes it in its security argument: per database
+  column j a random degree-t polynomial f_j with f_j(0) = e_theta[j], server
+  i receives (f_1(alpha_i), ..., f_r(alpha_i)); the client interpolates the
+  servers' responses at 0.  The random coefficients are inputs.
 
 Parity is pinned for every function here (see ``tests/test_oracle_pins.py``):
 brute force on tiny inputs, closed forms, a hand-worked example, the LWE
@@ -68,6 +77,8 @@ def _load():
         lib.oracle_matvec_u32.argtypes = [P, U, U, P, P]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_answer_batch_mod.argtypes = [P, U, U, P, U, P, U, ctypes.c_uint32, P]
+        lib.oracle_answer_batch_mod.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -281,3 +292,99 @@ def brute_chor(rows_bits: list, qbits: list) -> int:
         if bit:
             acc ^= row
     return acc
+
+
+# --------------------------------------------------------------------------
+# Goldberg IT-PIR (the FTR instantiation, Section 5.1): database words are
+# bytes taken as elements of Z/p for a prime p < 2^32; queries are Shamir
+# shares; the server's response is the product over Z/p.
+# --------------------------------------------------------------------------
+def answer_batch_mod(D: np.ndarray, Q, p: int, rows=None) -> np.ndarray:
+    """``out[r, b] = (sum_j D[r, j] * Q[j, b]) mod p`` for ``Q`` of shape C x B."""
+    D = _as_db(D)
+    Q = _as_u32(Q)
+    p = int(p)
+    assert 2 <= p < 1 << 32
+    R, C = D.shape
+    assert Q.ndim == 2 and Q.shape[0] == C
+    B = Q.shape[1]
+    if rows is None:
+        m, rp = R, None
+    else:
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.uint64))
+        assert rows.size == 0 or int(rows.max()) < R
+        m, rp = rows.size, _p(rows)
+    out = np.zeros((m, B), dtype=np.uint32)
+    if m and B:
+        rc = _load().oracle_answer_batch_mod(_p(D), C, C, rp, m, _p(Q), B, p, _p(out))
+        assert rc == 0, "oracle_answer_batch_mod: out of memory"
+    return out
+
+
+def answer_mod_entries(D_rows: np.ndarray, Q_cols: np.ndarray, p: int) -> np.ndarray:
+    """Sampled entries of ``D Q mod p``: entry k is ``D_rows[k] . Q_cols[k] mod p``.
+
+    D_rows: K x C bytes, Q_cols: K x C words.  The dot products are formed in
+    uint64, exact while C * 255 * (2^32 - 1) < 2^64, i.e. C < 2^24.
+    """
+    D_rows = np.asarray(D_rows, dtype=np.uint8)
+    Q_cols = np.asarray(Q_cols, dtype=np.uint32)
+    assert D_rows.shape == Q_cols.shape and D_rows.shape[1] < 1 << 24
+    tot = np.einsum("kj,kj->k", D_rows.astype(np.uint64), Q_cols.astype(np.uint64))
+    return (tot % np.uint64(p)).astype(np.uint32)
+
+
+def brute_answer_batch_mod(D, Q, p: int) -> list:
+    C = len(Q)
+    B = len(Q[0]) if C else 0
+    return [[sum(int(D[r][j]) * int(Q[j][b]) for j in range(C)) % p for b in range(B)]
+            for r in range(len(D))]
+
+
+def shamir_shares(secret, coeffs, alphas, p: int) -> np.ndarray:
+    """Shares of a vector secret: ``out[i, j] = f_j(alphas[i]) mod p`` with
+    ``f_j(x) = secret[j] + sum_{k=1..t} coeffs[k-1, j] x^k``.
+
+    secret: r residues, coeffs: t x r residues (uniform draws), alphas:
+    distinct nonzero evaluation points, one per server.  Returns len(alphas)
+    x r uint32.
+    """
+    p = int(p)
+    secret = np.asarray(secret, dtype=np.uint64) % np.uint64(p)
+    coeffs = np.asarray(coeffs, dtype=np.uint64).reshape(-1, secret.size)
+    out = np.empty((len(alphas), secret.size), dtype=np.uint32)
+    P = np.uint64(p)
+    for i, a in enumerate(alphas):
+        acc = secret.copy()
+        for k in range(coeffs.shape[0]):
+            ak = np.uint64(pow(int(a), k + 1, p))            # alpha^k mod p, < 2^32
+            acc = (acc + (coeffs[k] % P) * ak % P) % P       # products < 2^64
+        out[i] = acc.astype(np.uint32)
+    return out
+
+
+def lagrange_weights_at_zero(alphas, p: int) -> list:
+    """``w_i = prod_{m != i} alpha_m / (alpha_m - alpha_i) mod p``, so that a
+    polynomial of degree < len(alphas) has ``f(0) = sum_i w_i f(alpha_i)``."""
+    p = int(p)
+    al = [int(a) % p for a in alphas]
+    w = []
+    for i, ai in enumerate(al):
+        num, den = 1, 1
+        for m, am in enumerate(al):
+            if m != i:
+                num = num * am % p
+                den = den * (am - ai) % p
+        w.append(num * pow(den, -1, p) % p)
+    return w
+
+
+def lagrange_at_zero(alphas, responses, p: int) -> np.ndarray:
+    """Interpolate the servers' responses at 0: ``sum_i w_i R_i mod p``
+    (the client's reconstruction from any t+1 honest responses)."""
+    P = np.uint64(int(p))
+    w = lagrange_weights_at_zero(alphas, p)
+    acc = np.zeros(np.asarray(responses[0]).shape, dtype=np.uint64)
+    for wi, Ri in zip(w, responses):
+        acc = (acc + np.uint64(wi) * (np.asarray(Ri, dtype=np.uint64) % P) % P) % P
+    return acc.astype(np.uint32)

@@ -1,12 +1,13 @@
 /*
- * Plain CPU oracle for the LWE-form PIR Answer.  TEST INFRASTRUCTURE ONLY:
+ * Plain CPU oracle for the PIR Answer.  TEST INFRASTRUCTURE ONLY:
  * only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * may load this library.  It shares no code with the GPU path.
  *
  * What it computes follows the PIR interface of the paper (Definition 1: a
  * server turns a client query into a response derived from its local
  * database) in the single-server LWE form: the response is the database
- * matrix times the query vector over Z/2^32.  Every function is the plain
+ * matrix times the query vector over Z/2^32 (and, for the Goldberg
+ * instantiation, over Z/p).  Every function is the plain
  * definition written out as loops; unsigned 32-bit arithmetic in C wraps
  * modulo 2^32, which is exactly the ring the answer lives in.  No blocking,
  * no reordering beyond the definition's sum, no intrinsics.  OpenMP splits
@@ -15,6 +16,7 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -95,4 +97,40 @@ void oracle_matvec_u32(const uint32_t* M, uint64_t R, uint64_t n,
         for (uint64_t k = 0; k < n; ++k) acc += row[k] * x[k];
         y[r] = acc;
     }
+}
+
+/*
+ * Batched Answer over a prime field (the server product of the Goldberg /
+ * FTR instantiation, Section 5.1; Algorithm 4's batched product "mod q"):
+ *   out[i][b] = (sum_{j<C} D[rows[i]][j] * Q[j][b]) mod p
+ * The sum is formed exactly in unsigned 128-bit integers (each term is
+ * below 2^40) and reduced once.  Q: C x B words, out: m x B words,
+ * rows == NULL means rows[i] = i.  Returns -1 if the accumulator buffer
+ * cannot be allocated, else 0.
+ */
+int oracle_answer_batch_mod(const uint8_t* D, uint64_t C, uint64_t pitch,
+                            const uint64_t* rows, uint64_t m, const uint32_t* Q,
+                            uint64_t B, uint32_t p, uint32_t* out) {
+    int failed = 0;
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (int64_t)m; ++i) {
+        uint64_t r = rows ? rows[i] : (uint64_t)i;
+        const uint8_t* row = D + r * pitch;
+        unsigned __int128* acc = (unsigned __int128*)calloc(B ? B : 1, sizeof(unsigned __int128));
+        if (!acc) {
+#pragma omp atomic write
+            failed = 1;
+            continue;
+        }
+        for (uint64_t j = 0; j < C; ++j) {
+            uint64_t d = row[j];
+            const uint32_t* qj = Q + j * B;
+            for (uint64_t b = 0; b < B; ++b) acc[b] += (unsigned __int128)(d * (uint64_t)qj[b]);
+        }
+        uint32_t* o = out + (uint64_t)i * B;
+        for (uint64_t b = 0; b < B; ++b) o[b] = (uint32_t)(acc[b] % p);
+        free(acc);
+    }
+    return failed ? -1 : 0;
 }

@@ -60,6 +60,7 @@ SIGNATURES = {
     "pir_update_rows": (_ST, [_P, _P, _U32, _P, _P]),
     "pir_hint_update_rows": (_ST, [_P, _P, _U32, _P, _U32, _P, _P, _SZ, _P]),
     "pir_answer_batch_qmajor": (_ST, [_P, _P, _U32, _P, _P, _SZ, _P]),
+    "pir_answer_batch_modp": (_ST, [_P, _P, _U32, _U32, _P, _P, _SZ, _P]),
     "pir_variant_count": (_U32, [_U32]),
     "pir_variant_name": (ctypes.c_char_p, [_U32, _U32]),
     "pir_db_set_variant": (_ST, [_P, _U32, _U32]),
@@ -265,6 +266,28 @@ class Database:
         check(lib().pir_answer_batch_qmajor(self.handle, qp, B, op, wp, wn,
                                             _stream_ptr(stream, self.device)),
               "pir_answer_batch_qmajor")
+        return out
+
+    def answer_batch_modp(self, Q: torch.Tensor, p: int, out: torch.Tensor = None, stream=None,
+                          ws=None):
+        """``Out = D Q mod p`` for ``Q`` of shape C x B, ``2 <= p < 2^32``
+        (``pir_answer_batch_modp``, the Goldberg share product)."""
+        if Q.dim() != 2:
+            raise ValueError("Q must be C x B")
+        p = int(p)
+        if not 2 <= p < 1 << 32:
+            raise ValueError("p must be in [2, 2^32)")
+        B = int(Q.shape[1])
+        qp = _ptr_words(Q, "Q", (self.cols, B), self.device)
+        if out is None:
+            out = torch.empty((self.rows, B), dtype=torch.int32, device=self.device)
+        op = _ptr_words(out, "out", (self.rows, B), self.device)
+        if ws is None:
+            ws = self.workspace(B)
+        wp, wn = self._ws_args(ws)
+        check(lib().pir_answer_batch_modp(self.handle, qp, B, p, op, wp, wn,
+                                          _stream_ptr(stream, self.device)),
+              "pir_answer_batch_modp")
         return out
 
     def set_variant(self, batch: int, variant) -> None:

@@ -1,33 +1,52 @@
 // Batched Answer and offline hint on the int8 matrix cores.
 //
-//   Out[r][b] = sum_j D[r][j] * Q[j][b]  mod 2^32
+//   Out[r][b] = sum_j D[r][j] * Q[j][b]   mod 2^32   (LWE form)
+//   Out[r][b] = sum_j D[r][j] * Q[j][b]   mod p      (field form, p < 2^32)
 //
-// (the multi-request response of Section 5.2, Algorithm 4's batched product,
-// here over Z/2^32; the hint H = D A is the same product with A in place of
-// Q, Section 5.3's offline work).
+// The LWE form is the multi-request response of Section 5.2 (Algorithm 4's
+// batched product, here over Z/2^32); the hint H = D A is the same product
+// with A in place of Q (Section 5.3's offline work).  The field form is the
+// server product of the Goldberg / FTR instantiation (Section 5.1), the
+// "mod q" of Algorithm 4.
 //
 // gfx950 has only signed int8 matrix instructions, so both operands are
 // centred.  With q = sum_k 2^(8k) q_k (byte limbs), q_k = q'_k + 128 and
-// D = D' + 128 (D' = D xor 0x80 read as int8, likewise q'_k):
+// D = D' + 128 (D' = D xor 0x80 read as int8, likewise q'_k), over the
+// integers:
 //
-//   D q = sum_k 2^(8k) (D' q'_k)  +  128 sum_k 2^(8k) colsum(q'_k)
+//   D q = sum_k 2^(8k) (D' q'_k)  +  128 (colsum(q) - C * 0x80808080)
 //                                 +  0x80808080 rowsum(D)
 //
-// and sum_k 2^(8k) colsum(q'_k) = colsum(q) - C * 0x80808080.  So one int8
-// GEMM with M = R, K = C and N = 4 * B (the four limb planes of every query
-// side by side) gives the products P_k = D' q'_k; the epilogue adds
-// P_0 + 2^8 P_1 + 2^16 P_2 + 2^24 P_3, the per-query column term and the
-// per-row term kept in the database handle.  Every step is exact modulo
-// 2^32: the int32 accumulators of the matrix instruction wrap modulo 2^32
-// (two's complement), and only the residue is ever used.
+// One int8 GEMM with M = R, K = C and N = 4 * B (the four limb planes of
+// every query side by side) gives the products P_k = D' q'_k; the epilogue
+// adds P_0 + 2^8 P_1 + 2^16 P_2 + 2^24 P_3 and the two terms (column sums
+// from the ingest kernel, row sums from the database handle).
+// * Modulo 2^32 the int32 accumulators wrap freely: only residues are used.
+// * The field form rebuilds D q exactly, modulo 2^64 (D q < 2^64 for
+//   C <= 2^23), and reduces it mod p.  A product P_k over K <= 2^17 columns
+//   lies in [-16256 K, 16384 K]: the int32 accumulator holds it exactly
+//   except for +2^31 (all products (-128)(-128) with K = 2^17), which reads
+//   back as -2^31, a value the true sum cannot take, and is mapped back.  So
+//   every accumulation in the field form covers at most 2^17 columns; longer
+//   rows are split along K (below).
+//
+// Split-K.  When the output tiles cannot fill the chip (few rows: the
+// incremental hint, short databases), or the field form needs it, the K
+// range is cut into S pieces; each workgroup writes its piece's limb
+// combination as a partial (4 bytes mod 2^32, or 8 bytes exact) and a
+// finishing kernel adds the S partials and the centring terms.
 //
 // Kernels
 //   k_zero_words  clear the column sums
-//   k_ingest      Q (C x B words) -> QL (N x Cp centred int8, K-contiguous),
-//                 colsum[b] += sum_j Q[j][b]
-//   k_gemm        int8 MFMA 32x32x32 tiles, LDS double staging through
-//                 registers, fused epilogue, optional row gather/scatter
-//                 (the incremental hint touches only refreshed rows).
+//   k_ingest      Q -> QL (N x Cp centred int8, K-contiguous) and exact
+//                 64-bit colsum[b] = sum_j Q[j][b]
+//   k_gemm_ring   int8 MFMA 32x32x32; global tiles go straight to LDS
+//                 (global_load_lds_dwordx4) into a ring of stages; fused
+//                 epilogue, optional row gather, optional split-K
+//   k_gemm_roles  the same with separate loader waves for D and QL
+//   k_gemm        register-staged LDS tiles, for databases the ring cannot
+//                 serve (unaligned rows or C not a multiple of 16)
+//   k_finish      sums split-K partials and adds the centring terms
 //
 // QL row index of (query b, limb k): n = (b / 32) * 128 + k * 32 + (b % 32),
 // so the four limbs of a query land in the same lane of four adjacent 32x32
@@ -38,9 +57,23 @@ namespace {
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+typedef unsigned long long u64;
 
 constexpr uint32_t kCentreWord = 0x80808080u;
-constexpr int kKPad = 256;      // QL rows are padded with zeros to a multiple of this
+constexpr int kKPad = 256;                    // QL rows are zero-padded to a multiple of this
+constexpr uint32_t kExactSpan = 1u << 17;     // columns one exact int32 accumulation may cover
+constexpr uint32_t kMaxExactCols = 1u << 23;  // D q < 2^64 and exact row sums
+constexpr uint32_t kMaxSplits = 16;           // split-K pieces chosen for occupancy
+
+// Epilogue modes.
+enum : int {
+    kFinal32 = 0,     // Out mod 2^32
+    kPart32 = 1,      // split partial sum_k 2^(8k) P_k mod 2^32 (no centring terms)
+    kFinalModP = 2,   // Out mod p
+    kPart64 = 3,      // split partial sum_k 2^(8k) P_k, exact (mod 2^64)
+};
 
 __global__ void k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,12 +84,12 @@ __global__ void k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
 // query matrix is Q[j * ldj + b * ldb].  The load is coalesced along b for
 // the row-major layout (ldb == 1) and along j for the query-major one
 // (QMAJOR, ldj == 1); both go through an LDS tile, then each thread writes
-// 32 limb bytes of one query.
+// 32 limb bytes of one query and the limb-0 threads add the exact column
+// sums.
 template <bool QMAJOR>
 __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, uint64_t ldj,
                                                 uint64_t ldb, uint32_t C, uint32_t B, uint32_t Cp,
-                                                int8_t* __restrict__ QL,
-                                                uint32_t* __restrict__ colsum) {
+                                                int8_t* __restrict__ QL, u64* __restrict__ colsum) {
     __shared__ uint32_t s[32][65];
     const int t = threadIdx.x;
     const uint32_t j0 = blockIdx.x * 64u;
@@ -86,7 +119,7 @@ __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, 
     const int half = t & 1;
     const uint32_t b = b0 + bb;
     uint32_t w[8];
-    uint32_t sum = 0;
+    u64 sum = 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         uint32_t word = 0;
@@ -111,7 +144,134 @@ __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, 
     }
 }
 
-// ---------------------------------------------------------------- GEMM
+// ---------------------------------------------------------------- epilogue
+struct Epi {
+    uint32_t M;                 // output rows (gathered rows, or R)
+    uint32_t B, R, C;
+    const uint32_t* rows;       // database row of output row i, or null
+    const u64* colsum;          // exact column sums, B words
+    const uint32_t* rowsum;     // exact row sums (handle metadata)
+    uint32_t* out;
+    uint64_t o_ldr, o_ldb;
+    void* part;                 // split-K partials [split][M][B]
+    uint32_t p;                 // modulus of the field form
+};
+
+__device__ inline uint32_t colterm32(const Epi& e, uint32_t b) {
+    return 128u * ((uint32_t)e.colsum[b] - e.C * kCentreWord);
+}
+
+__device__ inline u64 colterm64(const Epi& e, uint32_t b) {
+    return 128ull * (e.colsum[b] - (u64)e.C * kCentreWord);
+}
+
+// Exact value of a limb product read from its int32 accumulator (K <= 2^17).
+__device__ inline u64 limb64(int32_t v) {
+    return v == INT32_MIN ? (1ull << 31) : (u64)(int64_t)v;
+}
+
+// Output element (local row i, query b) from its four limb products.
+template <int MODE, bool GATHER>
+__device__ inline void epi_store(const Epi& e, uint32_t split, uint32_t i, uint32_t b, int32_t p0,
+                                 int32_t p1, int32_t p2, int32_t p3) {
+    if (i >= e.M || b >= e.B) return;
+    if (MODE == kFinal32 || MODE == kFinalModP) {
+        const uint32_t r = GATHER ? e.rows[i] : i;
+        if (r >= e.R) return;
+        uint32_t* dst = e.out + (uint64_t)r * e.o_ldr + (uint64_t)b * e.o_ldb;
+        if (MODE == kFinal32) {
+            *dst = (uint32_t)p0 + ((uint32_t)p1 << 8) + ((uint32_t)p2 << 16) +
+                   ((uint32_t)p3 << 24) + colterm32(e, b) + kCentreWord * e.rowsum[r];
+        } else {
+            const u64 v = limb64(p0) + (limb64(p1) << 8) + (limb64(p2) << 16) +
+                          (limb64(p3) << 24) + colterm64(e, b) + (u64)kCentreWord * e.rowsum[r];
+            *dst = (uint32_t)(v % e.p);
+        }
+    } else {
+        const uint64_t at = ((uint64_t)split * e.M + i) * e.B + b;
+        if (MODE == kPart32)
+            static_cast<uint32_t*>(e.part)[at] = (uint32_t)p0 + ((uint32_t)p1 << 8) +
+                                                 ((uint32_t)p2 << 16) + ((uint32_t)p3 << 24);
+        else
+            static_cast<u64*>(e.part)[at] =
+                limb64(p0) + (limb64(p1) << 8) + (limb64(p2) << 16) + (limb64(p3) << 24);
+    }
+}
+
+// Write a wave's accumulators through the epilogue: the four limb tiles of
+// query group g sit in acc[a][4g .. 4g+3] (C layout of the 32x32 MFMA: lane
+// holds column lane % 32, register v holds row 8 (v/4) + 4 (lane/32) + v%4).
+template <int MODE, bool GATHER, int TM, int TN>
+__device__ inline void epi_wave(const Epi& e, uint32_t split, const i32x16 (&acc)[TM][TN],
+                                uint32_t m_base, uint32_t n_base, int lane) {
+#pragma unroll
+    for (int g = 0; g < TN / 4; ++g) {
+        const uint32_t bq = n_base / 4u + 32u * g + (uint32_t)(lane & 31);
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const uint32_t i = m_base + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+                epi_store<MODE, GATHER>(e, split, i, bq, acc[a][4 * g][v], acc[a][4 * g + 1][v],
+                                        acc[a][4 * g + 2][v], acc[a][4 * g + 3][v]);
+            }
+        }
+    }
+}
+
+// Sum of the split partials plus the centring terms, one output per thread.
+template <bool EXACT>
+__global__ __launch_bounds__(256) void k_finish(Epi e, uint32_t splits) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)e.M * e.B) return;
+    const uint32_t i = (uint32_t)(idx / e.B), b = (uint32_t)(idx % e.B);
+    const uint32_t r = e.rows ? e.rows[i] : i;
+    if (r >= e.R) return;
+    const uint64_t plane = (uint64_t)e.M * e.B;
+    uint32_t* dst = e.out + (uint64_t)r * e.o_ldr + (uint64_t)b * e.o_ldb;
+    if (EXACT) {
+        u64 v = colterm64(e, b) + (u64)kCentreWord * e.rowsum[r];
+        const u64* part = static_cast<const u64*>(e.part) + idx;
+        for (uint32_t s = 0; s < splits; ++s) v += part[s * plane];
+        *dst = (uint32_t)(v % e.p);
+    } else {
+        uint32_t v = colterm32(e, b) + kCentreWord * e.rowsum[r];
+        const uint32_t* part = static_cast<const uint32_t*>(e.part) + idx;
+        for (uint32_t s = 0; s < splits; ++s) v += part[s * plane];
+        *dst = v;
+    }
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+// contiguous range of workgroup indices, so the tiles it runs at once are
+// neighbours (shared D rows and query tiles stay in its own L2).
+__device__ inline uint32_t xcd_remap(uint32_t bid, uint32_t nblk) {
+    const uint32_t per = nblk / 8u;
+    return bid < per * 8u ? (bid % 8u) * per + bid / 8u : bid;
+}
+
+// Tile of a (remapped) workgroup index, split-major: within a split, tiles
+// go in groups of 8 row tiles so the ~32 workgroups an XCD runs at once
+// share D and QL tiles in its L2.
+struct TileId {
+    uint32_t m, n, split;
+};
+
+__device__ inline TileId tile_of(uint32_t bid, uint32_t n_tiles, uint32_t m_tiles) {
+    constexpr uint32_t kGroup = 8;
+    const uint32_t tiles = n_tiles * m_tiles;
+    TileId t;
+    t.split = bid / tiles;
+    bid %= tiles;
+    const uint32_t first_m = (bid / (kGroup * n_tiles)) * kGroup;
+    const uint32_t gsize = min(m_tiles - first_m, kGroup);
+    const uint32_t in_group = bid % (kGroup * n_tiles);
+    t.m = first_m + in_group % gsize;
+    t.n = in_group / gsize;
+    return t;
+}
+
+// ---------------------------------------------------------------- GEMM, register-staged
 template <int WM_, int WN_, int TM_, int TN_, int BK_>
 struct Tile {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, BK = BK_;
@@ -139,40 +299,25 @@ __device__ inline u32x4 load_row16(const uint8_t* row, uint32_t k, uint32_t C) {
 }
 
 // Block tile BM x BN of Out; 4 waves in a WM x WN grid, each computing
-// (TM*32) x (TN*32) with 32x32x32 int8 MFMAs.
+// (TM*32) x (TN*32) with 32x32x32 int8 MFMAs; LDS tiles staged through
+// registers with one tile of prefetch.  LWE form, no split.
 template <class T, bool VEC, bool GATHER>
 __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uint64_t pitch,
-                                              uint32_t R, uint32_t C,
-                                              const uint32_t* __restrict__ rows, uint32_t M,
                                               const int8_t* __restrict__ QL, uint32_t Cp,
-                                              uint32_t B, uint32_t n_tiles,
-                                              const uint32_t* __restrict__ colsum,
-                                              const uint32_t* __restrict__ rowterm,
-                                              uint32_t* __restrict__ out, uint64_t o_ldr,
-                                              uint64_t o_ldb) {
+                                              uint32_t n_tiles, Epi e) {
     __shared__ __attribute__((aligned(16))) uint8_t sA[T::BM * T::LDK];
     __shared__ __attribute__((aligned(16))) uint8_t sB[T::BN * T::LDK];
+    const uint32_t R = e.R, C = e.C, M = e.M;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / T::WN;
     const int wn = wave % T::WN;
 
-    // Tiles are numbered n-fastest.  Consecutive workgroups are dealt to
-    // the 8 XCDs in turn; remap so each XCD works on a contiguous range of
-    // tiles (the row blocks of D it reads stay in its own L2).
-    const uint32_t nblk = gridDim.x;
-    uint32_t bid = blockIdx.x;
-    {
-        const uint32_t per = nblk / 8u;
-        const uint32_t x = bid % 8u, l = bid / 8u;
-        if (bid < per * 8u) bid = x * per + l;
-    }
-    const uint32_t tile_m = bid / n_tiles;
-    const uint32_t tile_n = bid % n_tiles;
-    const uint32_t m0 = tile_m * T::BM;
-    const uint32_t n0 = tile_n * T::BN;
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t m0 = (bid / n_tiles) * T::BM;
+    const uint32_t n0 = (bid % n_tiles) * T::BN;
 
     // Global load assignment: thread -> (row, 16-byte segment).
     const int seg = tid % T::SEGS;
@@ -184,7 +329,7 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
     for (int p = 0; p < T::A_LOADS; ++p) {
         uint32_t i = m0 + rsub + p * ROWS_PER_PASS;
         i = i < M ? i : M - 1;
-        const uint32_t r = GATHER ? rows[i] : i;
+        const uint32_t r = GATHER ? e.rows[i] : i;
         arow[p] = D + (uint64_t)(r < R ? r : R - 1) * pitch;
     }
     const int8_t* brow[T::B_LOADS];
@@ -252,45 +397,48 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
             __syncthreads();
         }
     }
+    epi_wave<kFinal32, GATHER, T::TM, T::TN>(e, 0, acc, m0 + wm * T::TM * 32,
+                                              n0 + wn * T::TN * 32, lane);
+}
 
-    // Epilogue: combine limbs, add the centring terms, store.
-    const uint32_t cterm_base = (uint32_t)C * kCentreWord;
-#pragma unroll
-    for (int g = 0; g < T::TN / 4; ++g) {
-        const uint32_t bq = (n0 + wn * T::TN * 32) / 4u + 32u * g + (uint32_t)(lane & 31);
-        const uint32_t colterm = 128u * (bq < B ? colsum[bq] - cterm_base : 0u);
-#pragma unroll
-        for (int a = 0; a < T::TM; ++a) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const uint32_t i = m0 + wm * T::TM * 32 + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-                if (i < M && bq < B) {
-                    const uint32_t r = GATHER ? rows[i] : i;
-                    if (r < R) {
-                        const uint32_t p0 = (uint32_t)acc[a][4 * g + 0][v];
-                        const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
-                        const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
-                        const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
-                        out[(uint64_t)r * o_ldr + (uint64_t)bq * o_ldb] =
-                            p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
-                    }
-                }
-            }
-        }
-    }
+// ---------------------------------------------------------------- LDS ring helpers
+// 16-byte slot of (row, segment) in an LDS row.  A fragment read has 32
+// lanes on 32 consecutive rows at one segment; gfx950's LDS serves a
+// 16-byte read 16 lanes at a time across 64 four-byte banks, so the 16 rows
+// of a pass must land on 16 distinct 16-byte bank groups.  A 64-byte row
+// spans 16 banks (row % 4 picks the quarter of the bank space), a 128-byte
+// row 32 banks (row % 2); XORing the segment with the next row bits fills
+// the remaining choices.  (Measured: a swizzle that is conflict-free for
+// 8 lanes over 32 banks spent half of the LDS cycles in bank conflicts.)
+template <int BK>
+__device__ inline int swz(int row, int seg) {
+    return BK == 64 ? (seg ^ ((row >> 2) & 3)) : (seg ^ ((row >> 1) & 7));
+}
+
+// s_waitcnt with only vmcnt constrained (gfx9 encoding: vmcnt low bits
+// [3:0], high bits [15:14]; expcnt and lgkmcnt left at their maximum).
+template <int N>
+__device__ inline void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Workgroup barrier without the memory fence of __syncthreads(): the fence
+// would drain every outstanding load (vmcnt(0)) and empty the ring.  Each
+// wave has already waited for its own tile loads (wait_vmcnt), and LDS
+// reads are not moved across the asm statements.
+__device__ inline void ring_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 // ---------------------------------------------------------------- GEMM, LDS ring
 // The main kernel for aligned databases with C a multiple of 16.  Global
 // tiles go straight to LDS with global_load_lds_dwordx4 (no register
-// staging), into a ring of STAGES k-tiles of 64 bytes, so STAGES-1 tiles are
-// in flight while one is consumed.  A 64-byte LDS row holds four 16-byte
-// slots; slot = segment ^ ((row >> 1) & 3) keeps the fragment reads
-// (one row per lane, same segment) free of bank conflicts.  Centring of D
-// (xor 0x80) is applied to the A fragments in registers.
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) void glb_void_t;
-
+// staging), into a ring of STAGES k-tiles of BK bytes, so STAGES-1 tiles are
+// in flight while one is consumed.  Centring of D (xor 0x80) is applied to
+// the A fragments in registers.
 template <int WM_, int WN_, int TM_, int TN_, int STAGES_, int BK_ = 64>
 struct Ring {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, STAGES = STAGES_;
@@ -315,78 +463,32 @@ struct Ring {
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
-// 16-byte slot of (row, segment) in an LDS row.  A fragment read has 32
-// lanes on 32 consecutive rows at one segment; gfx950's LDS serves a
-// 16-byte read 16 lanes at a time across 64 four-byte banks, so the 16 rows
-// of a pass must land on 16 distinct 16-byte bank groups.  A 64-byte row
-// spans 16 banks (row % 4 picks the quarter of the bank space), a 128-byte
-// row 32 banks (row % 2); XORing the segment with the next row bits fills
-// the remaining choices.  (Measured: the earlier swizzle, conflict-free for
-// 8 lanes over 32 banks, spent half of the LDS cycles in bank conflicts.)
-template <int BK>
-__device__ inline int swz(int row, int seg) {
-    return BK == 64 ? (seg ^ ((row >> 2) & 3)) : (seg ^ ((row >> 1) & 7));
-}
-
-__device__ inline int slot_of(int row, int seg) { return swz<64>(row, seg); }
-
-// s_waitcnt with only vmcnt constrained (gfx9 encoding: vmcnt low bits
-// [3:0], high bits [15:14]; expcnt and lgkmcnt left at their maximum).
-template <int N>
-__device__ inline void wait_vmcnt() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-}
-
-// Workgroup barrier without the memory fence of __syncthreads(): the fence
-// would drain every outstanding load (vmcnt(0)) and empty the ring.  Each
-// wave has already waited for its own tile loads (wait_vmcnt), and LDS
-// reads are not moved across the asm statements.
-__device__ inline void ring_barrier() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-
-template <class T, bool GATHER>
-__global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restrict__ D, uint64_t pitch,
-                                                   uint32_t R, uint32_t C,
-                                                   const uint32_t* __restrict__ rows, uint32_t M,
-                                                   const int8_t* __restrict__ QL, uint32_t Cp,
-                                                   uint32_t B, uint32_t n_tiles, uint32_t m_tiles,
-                                                   const uint32_t* __restrict__ colsum,
-                                                   const uint32_t* __restrict__ rowterm,
-                                                   uint32_t* __restrict__ out, uint64_t o_ldr,
-                                                   uint64_t o_ldb) {
+// Workgroup w covers tile tile_of(w) and, with split-K, the k-tiles
+// [split * kts, split * kts + kts) of its piece.
+template <class T, bool GATHER, int MODE>
+__global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restrict__ D,
+                                                          uint64_t pitch,
+                                                          const int8_t* __restrict__ QL,
+                                                          uint32_t Cp, uint32_t n_tiles,
+                                                          uint32_t m_tiles, uint32_t kts, Epi e) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const uint32_t R = e.R, C = e.C, M = e.M;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / T::WN;
     const int wn = wave % T::WN;
 
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous range of tile indices, then order tiles in groups of 8 row
-    // tiles so the ~32 workgroups an XCD runs at once share D and QL tiles
-    // in its L2.
-    uint32_t bid = blockIdx.x;
-    {
-        const uint32_t per = gridDim.x / 8u;
-        if (bid < per * 8u) bid = (bid % 8u) * per + bid / 8u;
-    }
-    constexpr uint32_t kGroup = 8;
-    const uint32_t group = bid / (kGroup * n_tiles);
-    const uint32_t first_m = group * kGroup;
-    const uint32_t gsize = min(m_tiles - first_m, kGroup);
-    const uint32_t in_group = bid % (kGroup * n_tiles);
-    const uint32_t tile_m = first_m + in_group % gsize;
-    const uint32_t tile_n = in_group / gsize;
-    const uint32_t m0 = tile_m * T::BM;
-    const uint32_t n0 = tile_n * T::BN;
+    const TileId tl = tile_of(xcd_remap(blockIdx.x, gridDim.x), n_tiles, m_tiles);
+    const uint32_t m0 = tl.m * T::BM;
+    const uint32_t n0 = tl.n * T::BN;
+    const uint32_t ktiles_all = (C + T::BK - 1) / T::BK;
+    const uint32_t kt0 = tl.split * kts;
+    const uint32_t ktiles = kt0 < ktiles_all ? min(kts, ktiles_all - kt0) : 0u;
 
     // Per-lane source of each of this wave's LOADS block loads: lane l of a
     // load fills slot l % SEGS of row l / SEGS of a 1 KiB block.
-    const int lrow = lane / T::SEGS;                      // row within a 1 KiB block
+    const int lrow = lane / T::SEGS;
     const uint8_t* src[T::LOADS];
     uint32_t seg_off[T::LOADS];
     bool is_a[T::LOADS];
@@ -401,18 +503,17 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
         if (a) {
             uint32_t mi = m0 + r;
             mi = mi < M ? mi : M - 1;
-            uint32_t dr = GATHER ? rows[mi] : mi;
+            uint32_t dr = GATHER ? e.rows[mi] : mi;
             dr = dr < R ? dr : R - 1;
             src[i] = D + (uint64_t)dr * pitch + seg_off[i];
         } else {
             src[i] = reinterpret_cast<const uint8_t*>(QL) + (uint64_t)(n0 + r) * Cp + seg_off[i];
         }
     }
-    const uint32_t ktiles = (C + T::BK - 1) / T::BK;
 
-    auto issue = [&](uint32_t t) {
-        const uint32_t k0 = t * T::BK;
-        uint8_t* stage = smem + (t % T::STAGES) * T::STAGE_BYTES;
+    auto issue = [&](uint32_t u) {
+        const uint32_t k0 = (kt0 + u) * T::BK;
+        uint8_t* stage = smem + (u % T::STAGES) * T::STAGE_BYTES;
 #pragma unroll
         for (int i = 0; i < T::LOADS; ++i) {
             const int kb = wave + T::NW * i;
@@ -442,20 +543,20 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     for (int p = 0; p < T::STAGES - 1; ++p)
         if ((uint32_t)p < ktiles) issue(p);
 
-    for (uint32_t t = 0; t < ktiles; ++t) {
-        // Tiles t+1 .. t+STAGES-2 were issued after tile t.  While none of
-        // them is the last tile (whose D loads past column C may be skipped
-        // by a whole wave, issuing fewer loads), tile t has landed once at
-        // most (STAGES-2) * LOADS of this wave's loads are outstanding
-        // (loads complete in order).  Otherwise wait for all.  The barrier
-        // then makes every wave's part visible and frees the stage consumed
-        // in the previous iteration.
-        if (t + T::STAGES - 1 < ktiles) wait_vmcnt<(T::STAGES - 2) * T::LOADS>();
+    for (uint32_t u = 0; u < ktiles; ++u) {
+        // Tiles u+1 .. u+STAGES-2 were issued after tile u.  While none of
+        // them is the piece's last tile (whose D loads past column C may be
+        // skipped by a whole wave, issuing fewer loads), tile u has landed
+        // once at most (STAGES-2) * LOADS of this wave's loads are
+        // outstanding (loads complete in order).  Otherwise wait for all.
+        // The barrier then makes every wave's part visible and frees the
+        // stage consumed in the previous iteration.
+        if (u + T::STAGES - 1 < ktiles) wait_vmcnt<(T::STAGES - 2) * T::LOADS>();
         else wait_vmcnt<0>();
         ring_barrier();
-        if (t + T::STAGES - 1 < ktiles) issue(t + T::STAGES - 1);
+        if (u + T::STAGES - 1 < ktiles) issue(u + T::STAGES - 1);
 
-        const uint8_t* sa = smem + (t % T::STAGES) * T::STAGE_BYTES;
+        const uint8_t* sa = smem + (u % T::STAGES) * T::STAGE_BYTES;
         const uint8_t* sb = sa + T::A_BYTES;
         // Fragments of k-step ks+1 are read while the MFMAs of ks run.
         constexpr int KS = T::BK / 32;
@@ -488,30 +589,8 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
         }
     }
 
-    const uint32_t cterm_base = C * kCentreWord;
-#pragma unroll
-    for (int g = 0; g < T::TN / 4; ++g) {
-        const uint32_t bq = (n0 + wn * T::TN * 32) / 4u + 32u * g + (uint32_t)(lane & 31);
-        const uint32_t colterm = 128u * (bq < B ? colsum[bq] - cterm_base : 0u);
-#pragma unroll
-        for (int a = 0; a < T::TM; ++a) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const uint32_t i = m0 + wm * T::TM * 32 + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-                if (i < M && bq < B) {
-                    const uint32_t r = GATHER ? rows[i] : i;
-                    if (r < R) {
-                        const uint32_t p0 = (uint32_t)acc[a][4 * g + 0][v];
-                        const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
-                        const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
-                        const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
-                        out[(uint64_t)r * o_ldr + (uint64_t)bq * o_ldb] =
-                            p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
-                    }
-                }
-            }
-        }
-    }
+    epi_wave<MODE, GATHER, T::TM, T::TN>(e, tl.split, acc, m0 + wm * T::TM * 32,
+                                          n0 + wn * T::TN * 32, lane);
 }
 
 // ---------------------------------------------------------------- GEMM, split load roles
@@ -520,9 +599,9 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
 // latency) can only run as far ahead as the shorter ring allows.  Here waves
 // 0-1 load only D tiles into a deep ring of SA stages and waves 2-3 load only
 // query tiles into a ring of SB stages; each wave waits on its own counter,
-// then all four meet at the barrier and compute.
+// then all four meet at the barrier and compute.  LWE form, no split.
 template <int WM_, int WN_, int TM_, int TN_, int SA_, int SB_>
-struct Split {
+struct Roles {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, SA = SA_, SB = SB_;
     static constexpr int BK = 64;
     static constexpr int BM = WM * TM * 32;
@@ -540,16 +619,11 @@ struct Split {
 };
 
 template <class T, bool GATHER>
-__global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ D, uint64_t pitch,
-                                                    uint32_t R, uint32_t C,
-                                                    const uint32_t* __restrict__ rows, uint32_t M,
+__global__ __launch_bounds__(256) void k_gemm_roles(const uint8_t* __restrict__ D, uint64_t pitch,
                                                     const int8_t* __restrict__ QL, uint32_t Cp,
-                                                    uint32_t B, uint32_t n_tiles, uint32_t m_tiles,
-                                                    const uint32_t* __restrict__ colsum,
-                                                    const uint32_t* __restrict__ rowterm,
-                                                    uint32_t* __restrict__ out, uint64_t o_ldr,
-                                                    uint64_t o_ldb) {
+                                                    uint32_t n_tiles, uint32_t m_tiles, Epi e) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const uint32_t R = e.R, C = e.C, M = e.M;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -558,20 +632,9 @@ __global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ 
     const bool loads_d = wave < 2;
     const int lw = wave & 1;                               // index among the loader pair
 
-    uint32_t bid = blockIdx.x;
-    {
-        const uint32_t per = gridDim.x / 8u;
-        if (bid < per * 8u) bid = (bid % 8u) * per + bid / 8u;
-    }
-    constexpr uint32_t kGroup = 8;
-    const uint32_t group = bid / (kGroup * n_tiles);
-    const uint32_t first_m = group * kGroup;
-    const uint32_t gsize = min(m_tiles - first_m, kGroup);
-    const uint32_t in_group = bid % (kGroup * n_tiles);
-    const uint32_t tile_m = first_m + in_group % gsize;
-    const uint32_t tile_n = in_group / gsize;
-    const uint32_t m0 = tile_m * T::BM;
-    const uint32_t n0 = tile_n * T::BN;
+    const TileId tl = tile_of(xcd_remap(blockIdx.x, gridDim.x), n_tiles, m_tiles);
+    const uint32_t m0 = tl.m * T::BM;
+    const uint32_t n0 = tl.n * T::BN;
 
     constexpr int NL = T::A_LOADS > T::B_LOADS ? T::A_LOADS : T::B_LOADS;
     const uint8_t* src[NL];
@@ -586,7 +649,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ 
         if (loads_d) {
             uint32_t mi = m0 + (uint32_t)min(r, T::BM - 1);
             mi = mi < M ? mi : M - 1;
-            uint32_t dr = GATHER ? rows[mi] : mi;
+            uint32_t dr = GATHER ? e.rows[mi] : mi;
             dr = dr < R ? dr : R - 1;
             src[i] = D + (uint64_t)dr * pitch + seg_off[i];
         } else {
@@ -637,8 +700,8 @@ __global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ 
         if ((uint32_t)p < ktiles) issue(p);
 
     for (uint32_t t = 0; t < ktiles; ++t) {
-        // Each loader wave waits for its own part of tile t (see k_gemm_ring
-        // for the counting; only D loads of the last tile can be skipped).
+        // Each loader wave waits for its own part of tile t (counting as in
+        // k_gemm_ring; only D loads of the last tile can be skipped).
         if (loads_d) {
             if (t + T::SA - 1 < ktiles) wait_vmcnt<(T::SA - 2) * T::A_LOADS>();
             else wait_vmcnt<0>();
@@ -658,14 +721,14 @@ __global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ 
 #pragma unroll
             for (int a = 0; a < T::TM; ++a) {
                 const int r = wm * T::TM * 32 + a * 32 + frow;
-                u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * slot_of(r, seg));
+                u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * swz<64>(r, seg));
                 v ^= centre;
                 fa[a] = __builtin_bit_cast(i32x4, v);
             }
 #pragma unroll
             for (int b = 0; b < T::TN; ++b) {
                 const int r = wn * T::TN * 32 + b * 32 + frow;
-                fb[b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * slot_of(r, seg));
+                fb[b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * swz<64>(r, seg));
             }
 #pragma unroll
             for (int a = 0; a < T::TM; ++a)
@@ -674,100 +737,88 @@ __global__ __launch_bounds__(256) void k_gemm_split(const uint8_t* __restrict__ 
                     acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
         }
     }
-
-    const uint32_t cterm_base = C * kCentreWord;
-#pragma unroll
-    for (int g = 0; g < T::TN / 4; ++g) {
-        const uint32_t bq = (n0 + wn * T::TN * 32) / 4u + 32u * g + (uint32_t)(lane & 31);
-        const uint32_t colterm = 128u * (bq < B ? colsum[bq] - cterm_base : 0u);
-#pragma unroll
-        for (int a = 0; a < T::TM; ++a) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const uint32_t i = m0 + wm * T::TM * 32 + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-                if (i < M && bq < B) {
-                    const uint32_t r = GATHER ? rows[i] : i;
-                    if (r < R) {
-                        const uint32_t p0 = (uint32_t)acc[a][4 * g + 0][v];
-                        const uint32_t p1 = (uint32_t)acc[a][4 * g + 1][v];
-                        const uint32_t p2 = (uint32_t)acc[a][4 * g + 2][v];
-                        const uint32_t p3 = (uint32_t)acc[a][4 * g + 3][v];
-                        out[(uint64_t)r * o_ldr + (uint64_t)bq * o_ldb] =
-                            p0 + (p1 << 8) + (p2 << 16) + (p3 << 24) + colterm + rowterm[r];
-                    }
-                }
-            }
-        }
-    }
+    epi_wave<kFinal32, GATHER, T::TM, T::TN>(e, 0, acc, m0 + wm * T::TM * 32,
+                                              n0 + wn * T::TN * 32, lane);
 }
 
 // ---------------------------------------------------------------- dispatch
 struct Gemm {
     const pir_db_t* db;
-    const uint32_t* rows;   // gathered rows or null
-    uint32_t M;             // output rows
     const int8_t* QL;
-    uint32_t Cp, B, N;
-    const uint32_t* colsum;
-    uint32_t* out;
-    uint64_t o_ldr, o_ldb;
+    uint32_t Cp, N;
+    Epi e;
+    uint32_t splits, kts;   // split-K pieces and k-tiles per piece
+    bool exact;             // field form
 };
+
+uint32_t g_cus = 256;       // compute units of the device (set at init)
+
+uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+template <class T, bool GATHER, int MODE>
+pir_status launch_ring_mode(const Gemm& g, uint32_t n_tiles, uint32_t m_tiles, hipStream_t s) {
+    const uint64_t blocks = (uint64_t)n_tiles * m_tiles * g.splits;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    k_gemm_ring<T, GATHER, MODE><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
+        g.db->D, g.db->pitch, g.QL, g.Cp, n_tiles, m_tiles, g.kts, g.e);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
 
 template <class T>
 pir_status launch_ring(const Gemm& g, hipStream_t s) {
-    const uint32_t n_tiles = (g.N + T::BN - 1) / T::BN;
-    const uint32_t m_tiles = (g.M + T::BM - 1) / T::BM;
-    const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
-    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
-    const pir_db_t* db = g.db;
-    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
-    if (g.rows)
-        k_gemm_ring<T, true><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
-            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
-            db->rowterm, g.out, g.o_ldr, g.o_ldb);
-    else
-        k_gemm_ring<T, false><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
-            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
-            db->rowterm, g.out, g.o_ldr, g.o_ldb);
-    PIR_LAUNCH_CHECK();
-    return PIR_OK;
-}
-
-template <class T>
-pir_status launch_split(const Gemm& g, hipStream_t s) {
-    const uint32_t n_tiles = (g.N + T::BN - 1) / T::BN;
-    const uint32_t m_tiles = (g.M + T::BM - 1) / T::BM;
-    const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
-    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
-    const pir_db_t* db = g.db;
-    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
-    if (g.rows)
-        k_gemm_split<T, true><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
-            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
-            db->rowterm, g.out, g.o_ldr, g.o_ldb);
-    else
-        k_gemm_split<T, false><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
-            db->D, db->pitch, R, C, g.rows, g.M, g.QL, g.Cp, g.B, n_tiles, m_tiles, g.colsum,
-            db->rowterm, g.out, g.o_ldr, g.o_ldb);
-    PIR_LAUNCH_CHECK();
-    return PIR_OK;
-}
-
-template <class T>
-pir_status set_split_lds() {
-    if (hipFuncSetAttribute((const void*)k_gemm_split<T, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess ||
-        hipFuncSetAttribute((const void*)k_gemm_split<T, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess)
-        return PIR_ERR_DEVICE;
-    return PIR_OK;
+    const uint32_t n_tiles = ceil_div(g.N, T::BN);
+    const uint32_t m_tiles = ceil_div(g.e.M, T::BM);
+    const bool gather = g.e.rows != nullptr;
+    if (g.exact) {
+        if (gather) return PIR_ERR_UNSUPPORTED;
+        if (g.splits > 1) return launch_ring_mode<T, false, kPart64>(g, n_tiles, m_tiles, s);
+        return launch_ring_mode<T, false, kFinalModP>(g, n_tiles, m_tiles, s);
+    }
+    if (g.splits > 1) {
+        if (gather) return launch_ring_mode<T, true, kPart32>(g, n_tiles, m_tiles, s);
+        return launch_ring_mode<T, false, kPart32>(g, n_tiles, m_tiles, s);
+    }
+    if (gather) return launch_ring_mode<T, true, kFinal32>(g, n_tiles, m_tiles, s);
+    return launch_ring_mode<T, false, kFinal32>(g, n_tiles, m_tiles, s);
 }
 
 template <class T>
 pir_status set_ring_lds() {
-    if (hipFuncSetAttribute((const void*)k_gemm_ring<T, false>,
+    const void* fns[] = {
+        (const void*)k_gemm_ring<T, false, kFinal32>, (const void*)k_gemm_ring<T, true, kFinal32>,
+        (const void*)k_gemm_ring<T, false, kPart32>,  (const void*)k_gemm_ring<T, true, kPart32>,
+        (const void*)k_gemm_ring<T, false, kPart64>,  (const void*)k_gemm_ring<T, false, kFinalModP>,
+    };
+    for (const void* f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) !=
+            hipSuccess)
+            return PIR_ERR_DEVICE;
+    return PIR_OK;
+}
+
+template <class T>
+pir_status launch_roles(const Gemm& g, hipStream_t s) {
+    if (g.exact || g.splits != 1) return PIR_ERR_UNSUPPORTED;
+    const uint32_t n_tiles = ceil_div(g.N, T::BN);
+    const uint32_t m_tiles = ceil_div(g.e.M, T::BM);
+    const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    if (g.e.rows)
+        k_gemm_roles<T, true><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+            g.db->D, g.db->pitch, g.QL, g.Cp, n_tiles, m_tiles, g.e);
+    else
+        k_gemm_roles<T, false><<<(uint32_t)blocks, 256, T::LDS_BYTES, s>>>(
+            g.db->D, g.db->pitch, g.QL, g.Cp, n_tiles, m_tiles, g.e);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
+template <class T>
+pir_status set_roles_lds() {
+    if (hipFuncSetAttribute((const void*)k_gemm_roles<T, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess ||
-        hipFuncSetAttribute((const void*)k_gemm_ring<T, true>,
+        hipFuncSetAttribute((const void*)k_gemm_roles<T, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) != hipSuccess)
         return PIR_ERR_DEVICE;
     return PIR_OK;
@@ -775,75 +826,66 @@ pir_status set_ring_lds() {
 
 template <class T>
 pir_status launch_reg(const Gemm& g, hipStream_t s) {
-    const uint32_t n_tiles = (g.N + T::BN - 1) / T::BN;
-    const uint32_t m_tiles = (g.M + T::BM - 1) / T::BM;
+    if (g.exact || g.splits != 1) return PIR_ERR_UNSUPPORTED;
+    const uint32_t n_tiles = ceil_div(g.N, T::BN);
+    const uint32_t m_tiles = ceil_div(g.e.M, T::BM);
     const uint64_t blocks = (uint64_t)n_tiles * m_tiles;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
     const pir_db_t* db = g.db;
-    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
-#define PIR_GEMM(VEC, GATHER)                                                                \
-    k_gemm<T, VEC, GATHER><<<(uint32_t)blocks, 256, 0, s>>>(db->D, db->pitch, R, C, g.rows, g.M, \
-                                                             g.QL, g.Cp, g.B, n_tiles, g.colsum, \
-                                                             db->rowterm, g.out, g.o_ldr, g.o_ldb)
+#define PIR_GEMM(VEC, GATHER)                                                              \
+    k_gemm<T, VEC, GATHER><<<(uint32_t)blocks, 256, 0, s>>>(db->D, db->pitch, g.QL, g.Cp, \
+                                                             n_tiles, g.e)
+    const bool gather = g.e.rows != nullptr;
     if (db->aligned) {
-        if (g.rows) PIR_GEMM(true, true); else PIR_GEMM(true, false);
+        if (gather) PIR_GEMM(true, true); else PIR_GEMM(true, false);
     } else {
-        if (g.rows) PIR_GEMM(false, true); else PIR_GEMM(false, false);
+        if (gather) PIR_GEMM(false, true); else PIR_GEMM(false, false);
     }
 #undef PIR_GEMM
     PIR_LAUNCH_CHECK();
     return PIR_OK;
 }
 
-// Kernel variants of the batched product.  Ring variants need a 16-byte
-// aligned database with C a multiple of 16; 256-wide tiles need N a
-// multiple of 256 (batches above 32 queries, padded to 64).
-using Ring128x256S6 = Ring<2, 2, 2, 4, 6>;   // 144 KiB LDS
-using Ring128x256S4 = Ring<2, 2, 2, 4, 4>;   //  96 KiB
-using Ring256x256S4 = Ring<2, 2, 4, 4, 4>;   // 128 KiB, 128x128 per wave
-using Ring128x128S8 = Ring<4, 1, 1, 4, 8>;   // 128 KiB
-using Ring8w256x256S4 = Ring<4, 2, 2, 4, 4>;  // 8 waves, 128 KiB
-using Ring8w256x256S3 = Ring<4, 2, 2, 4, 3>;  // 8 waves,  96 KiB
-using Ring8w128x256S6 = Ring<4, 2, 1, 4, 6>;  // 8 waves, 144 KiB
-using Ring8w128x256K128S3 = Ring<4, 2, 1, 4, 3, 128>;  // 8 waves, 144 KiB, 128-byte stages
-using Ring128x256K128S3 = Ring<2, 2, 2, 4, 3, 128>;    // 144 KiB
-using Ring8w256x256K128S2 = Ring<4, 2, 2, 4, 2, 128>;  // 8 waves, 128 KiB
-using Ring128x128K128S4 = Ring<4, 1, 1, 4, 4, 128>;    // 128 KiB
-using Split128x256A10B4 = Split<2, 2, 2, 4, 10, 4>;   // 80 + 64 KiB
-using Split128x256A12B3 = Split<2, 2, 2, 4, 12, 3>;   // 96 + 48 KiB
-using Split256x256A5B4 = Split<2, 2, 4, 4, 5, 4>;     // 80 + 64 KiB
-using Split128x128A12B6 = Split<4, 1, 1, 4, 12, 6>;   // 96 + 48 KiB
+// Kernel variants of the batched product.  Ring and roles variants need a
+// 16-byte aligned database with C a multiple of 16; 256-wide tiles need N a
+// multiple of 256 (batches above 32 queries, padded to 64).  Only ring
+// variants split K (and so serve the field form).
+using Ring128x128S8 = Ring<4, 1, 1, 4, 8>;              // 128 KiB LDS
+using Ring128x128K128S4 = Ring<4, 1, 1, 4, 4, 128>;     // 128 KiB, 128-byte stages
+using Ring128x256S6 = Ring<2, 2, 2, 4, 6>;              // 144 KiB
+using Ring8w128x256K128S3 = Ring<4, 2, 1, 4, 3, 128>;   // 8 waves, 144 KiB
+using Ring8w256x256S4 = Ring<4, 2, 2, 4, 4>;            // 8 waves, 128 KiB
+using Ring8w256x256K128S2 = Ring<4, 2, 2, 4, 2, 128>;   // 8 waves, 128 KiB
+using Roles256x256A5B4 = Roles<2, 2, 4, 4, 5, 4>;       // 80 + 64 KiB
+using Roles128x256A10B4 = Roles<2, 2, 2, 4, 10, 4>;     // 80 + 64 KiB
 using Reg128x256 = Tile<2, 2, 2, 4, 128>;
 using Reg128x128 = Tile<4, 1, 1, 4, 128>;
 
+enum Kind : uint8_t { kAuto, kRing, kRoles, kReg };
+
 struct VariantInfo {
     const char* name;
-    bool ring;
-    uint32_t bn;
+    Kind kind;
+    uint32_t bm, bn, bk;
     pir_status (*launch)(const Gemm&, hipStream_t);
 };
 
 const VariantInfo kVariants[] = {
-    {"auto", false, 0, nullptr},
-    {"ring_128x256_s6", true, 256, launch_ring<Ring128x256S6>},
-    {"ring_128x256_s4", true, 256, launch_ring<Ring128x256S4>},
-    {"ring_256x256_s4", true, 256, launch_ring<Ring256x256S4>},
-    {"ring_128x128_s8", true, 128, launch_ring<Ring128x128S8>},
-    {"reg_128x256", false, 256, launch_reg<Reg128x256>},
-    {"reg_128x128", false, 128, launch_reg<Reg128x128>},
-    {"split_128x256_a10b4", true, 256, launch_split<Split128x256A10B4>},
-    {"split_128x256_a12b3", true, 256, launch_split<Split128x256A12B3>},
-    {"split_256x256_a5b4", true, 256, launch_split<Split256x256A5B4>},
-    {"split_128x128_a12b6", true, 128, launch_split<Split128x128A12B6>},
-    {"ring8w_256x256_s4", true, 256, launch_ring<Ring8w256x256S4>},
-    {"ring8w_256x256_s3", true, 256, launch_ring<Ring8w256x256S3>},
-    {"ring8w_128x256_s6", true, 256, launch_ring<Ring8w128x256S6>},
-    {"ring8w_128x256_k128_s3", true, 256, launch_ring<Ring8w128x256K128S3>},
-    {"ring_128x256_k128_s3", true, 256, launch_ring<Ring128x256K128S3>},
-    {"ring8w_256x256_k128_s2", true, 256, launch_ring<Ring8w256x256K128S2>},
-    {"ring_128x128_k128_s4", true, 128, launch_ring<Ring128x128K128S4>},
+    {"auto", kAuto, 0, 0, 0, nullptr},
+    {"ring_128x128_s8", kRing, 128, 128, 64, launch_ring<Ring128x128S8>},
+    {"ring_128x128_k128_s4", kRing, 128, 128, 128, launch_ring<Ring128x128K128S4>},
+    {"ring_128x256_s6", kRing, 128, 256, 64, launch_ring<Ring128x256S6>},
+    {"ring8w_128x256_k128_s3", kRing, 128, 256, 128, launch_ring<Ring8w128x256K128S3>},
+    {"ring8w_256x256_s4", kRing, 256, 256, 64, launch_ring<Ring8w256x256S4>},
+    {"ring8w_256x256_k128_s2", kRing, 256, 256, 128, launch_ring<Ring8w256x256K128S2>},
+    {"roles_256x256_a5b4", kRoles, 256, 256, 64, launch_roles<Roles256x256A5B4>},
+    {"roles_128x256_a10b4", kRoles, 128, 256, 64, launch_roles<Roles128x256A10B4>},
+    {"reg_128x256", kReg, 128, 256, 128, launch_reg<Reg128x256>},
+    {"reg_128x128", kReg, 128, 128, 128, launch_reg<Reg128x128>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 9,
+                   kVarReg128 = 10;
 
 bool ring_ok(const pir_db_t* db) { return db->aligned && (db->cols % 16 == 0); }
 
@@ -853,53 +895,129 @@ bool variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
     if (v == 0) return true;
     if (v >= kNumVariants) return false;
     const VariantInfo& vi = kVariants[v];
-    if (vi.ring && !ring_ok(db)) return false;
+    if (vi.kind != kReg && !ring_ok(db)) return false;
     return (4u * padded_batch(B)) % vi.bn == 0;
 }
 
 uint32_t default_variant(const pir_db_t* db, uint32_t B) {
-    const bool narrow = padded_batch(B) == 32u;
-    if (ring_ok(db)) return narrow ? 4u : 1u;
-    return narrow ? 6u : 5u;
+    const uint32_t Bp = padded_batch(B);
+    if (!ring_ok(db)) return Bp == 32u ? kVarReg128 : kVarReg256;
+    if (Bp == 32u) return kVarRing128;
+    return Bp >= 256u ? kVarRingWide : kVarRing256;
+}
+
+struct SplitPlan {
+    uint32_t splits, kts;
+};
+
+// Split-K plan for a ring variant.  Ring workgroups hold 128-144 KiB of LDS,
+// one per CU, so a launch runs in ceil(tiles * S / CUs) rounds of 1/S of the
+// K range each; pick the S (up to kMaxSplits, at least two k-tiles per
+// piece) that minimises that time, with a small charge per piece for the
+// partials and the pipeline fill, considered only below two rounds of
+// tiles.  The field form also caps each piece at kExactSpan columns.
+SplitPlan plan_splits(uint32_t M, uint32_t N, uint32_t C, const VariantInfo& vi, bool exact) {
+    const uint32_t ktiles = ceil_div(C, vi.bk);
+    if (vi.kind != kRing || ktiles == 0) return {1u, ktiles};
+    const uint64_t tiles = (uint64_t)ceil_div(M, vi.bm) * ceil_div(N, vi.bn);
+    const uint32_t lo = exact ? ceil_div(ktiles, kExactSpan / vi.bk) : 1u;
+    uint32_t best = lo;
+    if (tiles < 2ull * g_cus) {
+        const uint32_t hi = std::max(lo, std::min(kMaxSplits, ktiles / 2));
+        double best_t = 1e30;
+        for (uint32_t sp = lo; sp <= hi; ++sp) {
+            const double t = (double)ceil_div(tiles * sp, g_cus) / sp + 0.005 * sp;
+            if (t < best_t) {
+                best_t = t;
+                best = sp;
+            }
+        }
+    }
+    const uint32_t kts = ceil_div(ktiles, best);
+    return {ceil_div(ktiles, kts), kts};
 }
 
 struct BatchLayout {
     uint32_t Bp, N, Cp;
-    size_t ql_bytes, colsum_off, total;
+    size_t colsum_off, part_off, total;
 };
 
+// Largest (splits x output rows) of any split-K plan for N limb columns:
+// every ring variant valid for N, every output row count up to R (gathered
+// calls have fewer rows, and so may split more), both forms.
+uint64_t worst_split_rows(const pir_db_t* db, uint32_t N) {
+    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
+    const bool exact_ok = C <= kMaxExactCols;
+    uint64_t worst = 0;   // splits x rows
+    for (uint32_t v = 1; v < kNumVariants; ++v) {
+        const VariantInfo& vi = kVariants[v];
+        if (vi.kind != kRing || N % vi.bn) continue;
+        const uint32_t nt = N / vi.bn;
+        const uint32_t mt_all = ceil_div(R, vi.bm);
+        // Row counts where the plan may split for occupancy, then R itself.
+        const uint32_t mt_hi = std::min<uint64_t>(mt_all, (2ull * g_cus + nt - 1) / nt);
+        for (uint32_t mt = 1; mt <= mt_hi + 1 && mt <= mt_all; ++mt) {
+            const uint32_t M = mt == mt_all ? R : mt * vi.bm;
+            for (int x = 0; x <= (exact_ok ? 1 : 0); ++x) {
+                const SplitPlan sp = plan_splits(M, N, C, vi, x == 1);
+                if (sp.splits > 1) worst = std::max<uint64_t>(worst, (uint64_t)sp.splits * M);
+            }
+        }
+        for (int x = 0; x <= (exact_ok ? 1 : 0); ++x) {
+            const SplitPlan sp = plan_splits(R, N, C, vi, x == 1);
+            if (sp.splits > 1) worst = std::max<uint64_t>(worst, (uint64_t)sp.splits * R);
+        }
+    }
+    return worst;
+}
+
+// Split-K partial bytes the workspace reserves for batch B (8 bytes per
+// partial).  The scan above costs tens of microseconds, so its result is
+// kept in the handle per padded-batch bucket (racing writers store the same
+// value).
+size_t partial_bound(const pir_db_t* db, uint32_t B, uint32_t N) {
+    if (!ring_ok(db)) return 0;
+    std::atomic<uint64_t>& slot = db->split_rows[batch_bucket(N / 4)];
+    uint64_t cached = slot.load(std::memory_order_relaxed);
+    uint64_t worst;
+    if (cached != 0 && (cached >> 40) == N) {
+        worst = cached & ((1ull << 40) - 1);
+    } else {
+        worst = worst_split_rows(db, N);
+        slot.store(((uint64_t)N << 40) | worst, std::memory_order_relaxed);
+    }
+    return worst ? round_up((size_t)worst * B * 8, kWsAlign) : 0;
+}
+
+// Workspace: limb planes, exact column sums, split-K partials.
 BatchLayout batch_layout(const pir_db_t* db, uint32_t B) {
     BatchLayout L;
-    // One group of 32 queries uses a 128-wide tile; larger batches are
-    // padded to whole 256-wide tiles (64 queries).  Padded queries are zero.
     L.Bp = padded_batch(B);
     L.N = 4u * L.Bp;
     L.Cp = (uint32_t)round_up(db->cols, kKPad);
-    L.ql_bytes = round_up((size_t)L.N * L.Cp, kWsAlign);
-    L.colsum_off = L.ql_bytes;
-    L.total = L.colsum_off + round_up((size_t)L.Bp * 4, kWsAlign);
+    L.colsum_off = round_up((size_t)L.N * L.Cp, kWsAlign);
+    L.part_off = L.colsum_off + round_up((size_t)L.Bp * 8, kWsAlign);
+    L.total = L.part_off + partial_bound(db, B, L.N);
     return L;
 }
 
 }  // namespace
 
 pir_status mfma_init() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+        g_cus = (uint32_t)cus;
     pir_status st;
-    if ((st = set_ring_lds<Ring128x256S6>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring128x256S4>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring256x256S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring128x128S8>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring8w256x256S4>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring8w256x256S3>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring8w128x256S6>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring8w128x256K128S3>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring128x256K128S3>()) != PIR_OK) return st;
-    if ((st = set_ring_lds<Ring8w256x256K128S2>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring128x128K128S4>()) != PIR_OK) return st;
-    if ((st = set_split_lds<Split128x256A10B4>()) != PIR_OK) return st;
-    if ((st = set_split_lds<Split128x256A12B3>()) != PIR_OK) return st;
-    if ((st = set_split_lds<Split256x256A5B4>()) != PIR_OK) return st;
-    return set_split_lds<Split128x128A12B6>();
+    if ((st = set_ring_lds<Ring128x256S6>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w128x256K128S3>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w256x256S4>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w256x256K128S2>()) != PIR_OK) return st;
+    if ((st = set_roles_lds<Roles256x256A5B4>()) != PIR_OK) return st;
+    return set_roles_lds<Roles128x256A10B4>();
 }
 
 uint32_t mfma_variant_count() { return kNumVariants; }
@@ -916,16 +1034,20 @@ size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B) {
 }
 
 pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
-                             const uint32_t* rows, uint32_t m, void* ws, size_t ws_bytes,
-                             hipStream_t s) {
+                             const uint32_t* rows, uint32_t m, uint32_t modulus, void* ws,
+                             size_t ws_bytes, hipStream_t s) {
+    const uint32_t C = (uint32_t)db->cols;
+    const bool exact = modulus != 0;
+    if (exact && (!ring_ok(db) || rows)) return PIR_ERR_UNSUPPORTED;
+    if (exact && C > kMaxExactCols) return PIR_ERR_SHAPE;
     const BatchLayout L = batch_layout(db, B);
     if (!ws || ws_bytes < L.total || ((uintptr_t)ws % kWsAlign)) return PIR_ERR_WORKSPACE;
     uint8_t* base = static_cast<uint8_t*>(ws);
     int8_t* QL = reinterpret_cast<int8_t*>(base);
-    uint32_t* colsum = reinterpret_cast<uint32_t*>(base + L.colsum_off);
-    const uint32_t C = (uint32_t)db->cols;
+    u64* colsum = reinterpret_cast<u64*>(base + L.colsum_off);
 
-    k_zero_words<<<(L.Bp + 255) / 256, 256, 0, s>>>(colsum, L.Bp);
+    k_zero_words<<<(2 * L.Bp + 255) / 256, 256, 0, s>>>(reinterpret_cast<uint32_t*>(colsum),
+                                                         2 * L.Bp);
     PIR_LAUNCH_CHECK();
     dim3 ig(L.Cp / 64, L.Bp / 32);
     if (io.q_ldj == 1)
@@ -937,7 +1059,32 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
     const uint32_t M = rows ? m : (uint32_t)db->rows;
     if (M == 0) return PIR_OK;
     uint32_t v = db->variant[batch_bucket(B)];
-    if (!variant_valid(db, B, v) || v == 0) v = default_variant(db, B);
-    const Gemm g{db, rows, M, QL, L.Cp, B, L.N, colsum, io.out, io.o_ldr, io.o_ldb};
-    return kVariants[v].launch(g, s);
+    if (v == 0 || !variant_valid(db, B, v)) v = default_variant(db, B);
+    if (exact && kVariants[v].kind != kRing) v = default_variant(db, B);
+    const VariantInfo& vi = kVariants[v];
+    const SplitPlan sp = plan_splits(M, L.N, C, vi, exact);
+    if (sp.splits > 1 && L.part_off + (size_t)sp.splits * M * B * 8 > L.total)
+        return PIR_ERR_WORKSPACE;   // cannot happen: the layout bounds every plan
+
+    Gemm g;
+    g.db = db;
+    g.QL = QL;
+    g.Cp = L.Cp;
+    g.N = L.N;
+    g.exact = exact;
+    g.splits = sp.splits;
+    g.kts = sp.kts;
+    g.e = Epi{M,          B,       (uint32_t)db->rows, C, rows, colsum, db->rowsum, io.out,
+              io.o_ldr,   io.o_ldb, base + L.part_off, modulus};
+    pir_status st = vi.launch(g, s);
+    if (st != PIR_OK || sp.splits <= 1) return st;
+    const uint64_t n = (uint64_t)M * B;
+    if (n == 0) return PIR_OK;
+    if ((n + 255) / 256 > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    if (exact)
+        k_finish<true><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, sp.splits);
+    else
+        k_finish<false><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, sp.splits);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
 }

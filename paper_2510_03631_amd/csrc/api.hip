@@ -66,17 +66,18 @@ pir_status pir_db_open(uint8_t* d_D, uint64_t rows, uint64_t cols, uint64_t row_
     db->pitch = row_pitch;
     db->device = dev;
     db->aligned = ((uintptr_t)d_D % 16 == 0) && (row_pitch % 16 == 0);
-    if (hipMalloc(&db->rowterm, rows * sizeof(uint32_t)) != hipSuccess) {
+    for (auto& slot : db->split_rows) slot.store(0, std::memory_order_relaxed);
+    if (hipMalloc(&db->rowsum, rows * sizeof(uint32_t)) != hipSuccess) {
         delete db;
         return PIR_ERR_NO_MEMORY;
     }
     db->magic = kDbMagic;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    pir_status st = launch_rowterm(db, nullptr, (uint32_t)rows, s);
+    pir_status st = launch_rowsum(db, nullptr, (uint32_t)rows, s);
     if (st == PIR_OK && hipStreamSynchronize(s) != hipSuccess) st = PIR_ERR_DEVICE;
     if (st != PIR_OK) {
         db->magic = 0;
-        (void)hipFree(db->rowterm);
+        (void)hipFree(db->rowsum);
         delete db;
         return st;
     }
@@ -92,7 +93,7 @@ pir_status pir_db_close(pir_db_t* db) {
     (void)hipSetDevice(db->device);
     pir_status st = PIR_OK;
     if (hipDeviceSynchronize() != hipSuccess) st = PIR_ERR_DEVICE;
-    if (hipFree(db->rowterm) != hipSuccess) st = PIR_ERR_DEVICE;
+    if (hipFree(db->rowsum) != hipSuccess) st = PIR_ERR_DEVICE;
     if (prev >= 0) (void)hipSetDevice(prev);
     db->magic = 0;
     delete db;
@@ -125,7 +126,7 @@ pir_status pir_answer_batch(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint3
     if (!d_Q || !d_out || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (B > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_Q, B, 1, d_out, B, 1};
-    return mfma_answer_batch(db, io, B, nullptr, 0, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, B, nullptr, 0, 0, d_ws, ws_bytes,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -137,7 +138,19 @@ pir_status pir_answer_batch_qmajor(pir_db_t* db, const uint32_t* d_Qt, uint32_t 
     if (!d_Qt || !d_outT || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (B > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_Qt, 1, db->cols, d_outT, 1, db->rows};
-    return mfma_answer_batch(db, io, B, nullptr, 0, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, B, nullptr, 0, 0, d_ws, ws_bytes,
+                             static_cast<hipStream_t>(stream));
+}
+
+pir_status pir_answer_batch_modp(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint32_t p,
+                                 uint32_t* d_out, void* d_ws, size_t ws_bytes,
+                                 pir_stream_t stream) {
+    if (!db_ok(db) || p < 2) return PIR_ERR_INVALID_ARG;
+    if (B == 0) return PIR_OK;
+    if (!d_Q || !d_out || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
+    if (B > kMaxBatch) return PIR_ERR_SHAPE;
+    const BatchIO io{d_Q, B, 1, d_out, B, 1};
+    return mfma_answer_batch(db, io, B, nullptr, 0, p, d_ws, ws_bytes,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -146,7 +159,7 @@ pir_status pir_setup_hint(pir_db_t* db, const uint32_t* d_A, uint32_t n, uint32_
     if (!db_ok(db) || !d_A || !d_H || n == 0 || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (n > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_A, n, 1, d_H, n, 1};
-    return mfma_answer_batch(db, io, n, nullptr, 0, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, n, nullptr, 0, 0, d_ws, ws_bytes,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -159,7 +172,7 @@ pir_status pir_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
     hipStream_t s = static_cast<hipStream_t>(stream);
     pir_status st = launch_scatter_rows(db, d_rows, m, d_new, s);
     if (st != PIR_OK) return st;
-    return launch_rowterm(db, d_rows, m, s);
+    return launch_rowsum(db, d_rows, m, s);
 }
 
 pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
@@ -171,7 +184,7 @@ pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m
     if (m > db->rows) return PIR_ERR_SHAPE;
     if (n > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_A, n, 1, d_H, n, 1};
-    return mfma_answer_batch(db, io, n, d_rows, m, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, n, d_rows, m, 0, d_ws, ws_bytes,
                              static_cast<hipStream_t>(stream));
 }
 

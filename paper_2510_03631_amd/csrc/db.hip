@@ -1,22 +1,20 @@
 // Database handle metadata and refresh kernels.
 //
-// The handle keeps one word per row, rowterm[r] = 0x80808080 * sum_j D[r][j]
-// (mod 2^32).  The matrix-core path works on centred bytes and limbs and
-// adds this term back (see answer_mfma.hip); it depends only on the
+// The handle keeps one word per row, rowsum[r] = sum_j D[r][j] (exact for
+// C < 2^24).  The matrix-core path works on centred bytes and limbs and adds
+// back a term built from it (see answer_mfma.hip); it depends only on the
 // database, so it is computed once when the handle is opened and again for
 // the rows a refresh rewrites.
 #include "qpir_internal.h"
 
 namespace {
 
-constexpr uint32_t kCentreWord = 0x80808080u;   // sum_k 2^(8k) * 128
-
 // One wave per row: byte sums through v_dot4_u32_u8 against 0x01010101.
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_rowterm(const uint8_t* __restrict__ D, uint64_t pitch,
+__global__ __launch_bounds__(256) void k_rowsum(const uint8_t* __restrict__ D, uint64_t pitch,
                                                  uint32_t R, uint32_t C,
                                                  const uint32_t* __restrict__ rows, uint32_t m,
-                                                 uint32_t* __restrict__ rowterm) {
+                                                 uint32_t* __restrict__ rowsum) {
     const int lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     for (uint32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < m; i += waves) {
@@ -39,7 +37,7 @@ __global__ __launch_bounds__(256) void k_rowterm(const uint8_t* __restrict__ D, 
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) rowterm[r] = kCentreWord * acc;
+        if (lane == 0) rowsum[r] = acc;
     }
 }
 
@@ -66,15 +64,15 @@ __global__ __launch_bounds__(256) void k_scatter_rows(uint8_t* __restrict__ D, u
 
 }  // namespace
 
-pir_status launch_rowterm(const pir_db_t* db, const uint32_t* rows, uint32_t m, hipStream_t s) {
+pir_status launch_rowsum(const pir_db_t* db, const uint32_t* rows, uint32_t m, hipStream_t s) {
     if (m == 0) return PIR_OK;
     const uint32_t blocks = (uint32_t)((m + 3) / 4 < 8192 ? (m + 3) / 4 : 8192);
     if (db->aligned)
-        k_rowterm<true><<<blocks, 256, 0, s>>>(db->D, db->pitch, (uint32_t)db->rows,
-                                               (uint32_t)db->cols, rows, m, db->rowterm);
+        k_rowsum<true><<<blocks, 256, 0, s>>>(db->D, db->pitch, (uint32_t)db->rows,
+                                               (uint32_t)db->cols, rows, m, db->rowsum);
     else
-        k_rowterm<false><<<blocks, 256, 0, s>>>(db->D, db->pitch, (uint32_t)db->rows,
-                                                (uint32_t)db->cols, rows, m, db->rowterm);
+        k_rowsum<false><<<blocks, 256, 0, s>>>(db->D, db->pitch, (uint32_t)db->rows,
+                                                (uint32_t)db->cols, rows, m, db->rowsum);
     PIR_LAUNCH_CHECK();
     return PIR_OK;
 }

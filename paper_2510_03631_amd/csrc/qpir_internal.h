@@ -5,6 +5,9 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <algorithm>
+#include <atomic>
+
 #include "qpir.h"
 
 constexpr int kBuckets = 24;   // batch-size buckets: 0 = single query, k = B in (2^(k-2), 2^(k-1)]
@@ -13,10 +16,13 @@ struct pir_db {
     uint32_t magic;        // kDbMagic while open
     uint8_t* D;            // borrowed database bytes
     uint64_t rows, cols, pitch;
-    uint32_t* rowterm;     // device, rows words: 0x80808080 * sum_j D[r][j]
+    uint32_t* rowsum;      // device, rows words: sum_j D[r][j]
     int device;
     bool aligned;          // D and pitch are multiples of 16
     uint8_t variant[kBuckets];   // kernel variant per batch bucket (0 = built-in choice)
+    // Cached split-K bound per padded-batch bucket: (N << 40) | (splits x rows),
+    // 0 when not yet computed (see answer_mfma.hip).
+    mutable std::atomic<uint64_t> split_rows[kBuckets];
 };
 
 constexpr uint32_t kDbMagic = 0x51504952u;   // "QPIR"
@@ -62,7 +68,7 @@ pir_status gemv_answer(const pir_db_t* db, const uint32_t* q, uint32_t* a, void*
                        size_t ws_bytes, hipStream_t s);
 
 // ---- database metadata (db.hip)
-pir_status launch_rowterm(const pir_db_t* db, const uint32_t* rows, uint32_t m, hipStream_t s);
+pir_status launch_rowsum(const pir_db_t* db, const uint32_t* rows, uint32_t m, hipStream_t s);
 pir_status launch_scatter_rows(const pir_db_t* db, const uint32_t* rows, uint32_t m,
                                const uint8_t* src, hipStream_t s);
 
@@ -72,6 +78,7 @@ uint32_t mfma_variant_count();
 const char* mfma_variant_name(uint32_t v);
 bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v);
 size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B);
+// modulus == 0: Out mod 2^32; otherwise Out mod modulus (field form).
 pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
-                             const uint32_t* rows, uint32_t m, void* ws, size_t ws_bytes,
-                             hipStream_t s);
+                             const uint32_t* rows, uint32_t m, uint32_t modulus, void* ws,
+                             size_t ws_bytes, hipStream_t s);

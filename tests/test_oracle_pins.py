@@ -280,3 +280,118 @@ def test_chor_reconstruction(servers):
     shares.append(last)
     resp = [oracle.chor_answer(DB, s) for s in shares]
     assert np.array_equal(oracle.chor_reconstruct(resp), DB[theta])
+
+
+# ---------------------------------------------------------------- Goldberg field form
+FIELD_PRIMES = (2, 257, 65537, 2147483647, workload.FTR_PRIME)
+
+
+def test_handworked_field(golden):
+    for case in golden["answer_mod"]:
+        D = np.array(case["D"], dtype=np.uint8)
+        Q = np.array(case["Q"], dtype=np.uint32)
+        assert oracle.answer_batch_mod(D, Q, case["p"]).tolist() == case["out"]
+        assert oracle.brute_answer_batch_mod(case["D"], case["Q"], case["p"]) == case["out"]
+
+
+def test_handworked_shamir(golden):
+    for case in golden["shamir"]:
+        p = case["p"]
+        sh = oracle.shamir_shares(case["secret"], case["coeffs"], case["alphas"], p)
+        assert sh.tolist() == case["shares"]
+        D = np.array(case["D"], dtype=np.uint8)
+        resp = [oracle.answer_batch_mod(D, sh[i][:, None], p)[:, 0] for i in range(len(sh))]
+        assert [r.tolist() for r in resp] == case["responses"]
+        assert oracle.lagrange_weights_at_zero(case["alphas"], p) == case["weights"]
+        assert oracle.lagrange_at_zero(case["alphas"], resp, p).tolist() == case["record"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_field_brute_force(seed):
+    g = np.random.default_rng(500 + seed)
+    R, C, B = (int(x) for x in g.integers(1, 9, size=3))
+    p = FIELD_PRIMES[seed % len(FIELD_PRIMES)]
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    Q = workload.uniform_u32(g, (C, B))          # words >= p are taken as integers
+    exp = oracle.brute_answer_batch_mod(D.tolist(), Q.tolist(), p)
+    assert oracle.answer_batch_mod(D, Q, p).tolist() == exp
+    rows = [R - 1, 0]
+    assert oracle.answer_batch_mod(D, Q, p, rows=rows).tolist() == [exp[R - 1], exp[0]]
+    ent = oracle.answer_mod_entries(D[[R - 1] * B], Q.T, p)
+    assert ent.tolist() == exp[R - 1]
+
+
+def test_field_equals_ring_when_no_reduction():
+    # With D Q below both p and 2^32, the field and ring answers are the same
+    # integer; the ring oracle is an independent loop.
+    g = np.random.default_rng(7)
+    D = g.integers(0, 256, size=(20, 64), dtype=np.uint8)
+    Q = g.integers(0, 1 << 16, size=(64, 5), dtype=np.uint32)   # D Q < 64 * 255 * 2^16 < 2^31
+    assert np.array_equal(oracle.answer_batch_mod(D, Q, workload.FTR_PRIME),
+                          oracle.answer_batch(D, Q))
+
+
+def test_field_closed_forms():
+    p = workload.FTR_PRIME
+    C = 1000
+    D = np.full((3, C), 255, dtype=np.uint8)
+    Q = np.full((C, 2), p - 1, dtype=np.uint32)                  # -1 mod p
+    assert np.all(oracle.answer_batch_mod(D, Q, p) == (-255 * C) % p)
+    # A unit query column returns the selected column of D (the record).
+    g = np.random.default_rng(8)
+    D = g.integers(0, 256, size=(9, 40), dtype=np.uint8)
+    E = np.zeros((40, 3), dtype=np.uint32)
+    for b, th in enumerate((0, 17, 39)):
+        E[th, b] = 1
+    assert np.array_equal(oracle.answer_batch_mod(D, E, p), D[:, [0, 17, 39]].astype(np.uint32))
+    # Linearity over Z/p.
+    Q1 = workload.uniform_mod(g, (40, 4), p)
+    Q2 = workload.uniform_mod(g, (40, 4), p)
+    Qs = ((Q1.astype(np.uint64) + Q2) % p).astype(np.uint32)
+    lhs = oracle.answer_batch_mod(D, Qs, p).astype(np.uint64)
+    rhs = (oracle.answer_batch_mod(D, Q1, p).astype(np.uint64) +
+           oracle.answer_batch_mod(D, Q2, p)) % p
+    assert np.array_equal(lhs, rhs)
+
+
+@pytest.mark.parametrize("p", [257, 65537, workload.FTR_PRIME])
+def test_lagrange_recovers_constant_term(p):
+    g = np.random.default_rng(p % 1000)
+    for t in (1, 2, 4):
+        coef = [int(c) for c in g.integers(0, p, size=t + 1)]
+        coef[-1] = coef[-1] or 1                                 # degree exactly t
+        f = lambda x: sum(c * pow(x, k, p) for k, c in enumerate(coef)) % p
+        alphas = [int(a) for a in g.choice(np.arange(1, min(p, 5000)), size=t + 1, replace=False)]
+        vals = [np.array([f(a)], dtype=np.uint32) for a in alphas]
+        assert int(oracle.lagrange_at_zero(alphas, vals, p)[0]) == coef[0]
+        # t points of a degree-t polynomial do not determine f(0) (here they
+        # miss it unless a 1/p coincidence happens).
+        if t >= 1 and p > 1000:
+            assert int(oracle.lagrange_at_zero(alphas[:t], vals[:t], p)[0]) != coef[0]
+
+
+@pytest.mark.parametrize("servers,t", [(3, 1), (5, 2), (6, 4)])
+def test_shamir_round_trip_recovers_record(servers, t):
+    p = workload.FTR_PRIME
+    g = np.random.default_rng(servers * 10 + t)
+    R, C = 11, 57                                   # 11 byte positions, 57 records
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    thetas = [3, 0, 56]
+    alphas = list(range(1, servers + 1))
+    # One share vector per retrieval per server: Q_i is C x len(thetas).
+    Qs = np.zeros((servers, C, len(thetas)), dtype=np.uint32)
+    for b, th in enumerate(thetas):
+        e = np.zeros(C, dtype=np.uint32)
+        e[th] = 1
+        sh = oracle.shamir_shares(e, workload.uniform_mod(g, (t, C), p), alphas, p)
+        Qs[:, :, b] = sh
+        assert not np.array_equal(sh[0], e)                    # shares hide e_theta
+    resp = [oracle.answer_batch_mod(D, Qs[i], p) for i in range(servers)]
+    want = D[:, thetas].astype(np.uint32)
+    # Any t + 1 responses reconstruct the records.
+    for pick in (list(range(t + 1)), list(range(servers - t - 1, servers))):
+        got = oracle.lagrange_at_zero([alphas[i] for i in pick], [resp[i] for i in pick], p)
+        assert np.array_equal(got, want)
+    # t responses do not.
+    got = oracle.lagrange_at_zero(alphas[:t], resp[:t], p)
+    assert not np.array_equal(got, want)

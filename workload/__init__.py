@@ -192,3 +192,33 @@ def chor_shares(g: np.random.Generator, rows: int, theta: int, servers: int) -> 
     per server (the last server's share is fixed by the client from these
     and theta).  Returns (servers - 1) x ceil(rows/32) words."""
     return chor_query_words(g, rows, servers - 1)
+
+
+# Goldberg IT-PIR (FTR instantiation) workloads: the same database sizes and
+# batches as the Chor ones.  The database is stored with one row per byte
+# position of a record and one column per record (R = 3072, C = records), so
+# a share vector over the records is one query column.  Words are bytes in
+# Z/p for the largest prime below 2^32.
+FTR_RECORD_BYTES = 3072
+FTR_RECORDS = CHOR_ROWS
+FTR_BATCHES = CHOR_BATCHES
+FTR_PRIME = 4294967291          # 2^32 - 5
+
+
+def uniform_mod(g: np.random.Generator, shape, p: int) -> np.ndarray:
+    """Uniform residues in [0, p) as uint32 (share polynomial coefficients,
+    or share-like query words)."""
+    return g.integers(0, int(p), size=shape, dtype=np.uint64).astype(np.uint32)
+
+
+def device_mod(shape, p: int, seed: int, device="cuda"):
+    """Uniform residues in [0, p) drawn on ``device``, as an int32 tensor
+    holding the uint32 bit patterns."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    t = torch.empty(shape, dtype=torch.int64, device=device)
+    t.random_(0, int(p), generator=gen)
+    t = torch.where(t >= (1 << 31), t - (1 << 32), t)
+    return t.to(torch.int32)
