@@ -37,8 +37,12 @@ def _time_call(fn, reps: int) -> float:
     return start.elapsed_time(stop) / reps * 1e3   # microseconds
 
 
-def tune_database(db: Database, batches, reps: int = 5, log=print) -> dict:
-    """Time every valid variant for each batch size; return {batch: {name: us}}."""
+def tune_database(db: Database, batches, reps: int = 5, log=print, modulus: int = 0) -> dict:
+    """Time every valid variant for each batch size; return {batch: {name: us}}.
+
+    With ``modulus`` set, batched calls are timed in the field form
+    (``answer_batch_modp``), which runs only the split-K capable variants.
+    """
     import torch
     results = {}
     for B in batches:
@@ -52,10 +56,13 @@ def tune_database(db: Database, batches, reps: int = 5, log=print) -> dict:
             Q = torch.randint(-2**31, 2**31 - 1, (db.cols, B), dtype=torch.int32, device=db.device)
             out = torch.empty((db.rows, B), dtype=torch.int32, device=db.device)
             ws = db.workspace(B)
-            fn = lambda: db.answer_batch(Q, out=out, ws=ws)
+            if modulus:
+                fn = lambda: db.answer_batch_modp(Q, modulus, out=out, ws=ws)
+            else:
+                fn = lambda: db.answer_batch(Q, out=out, ws=ws)
         times = {}
         for v, name in enumerate(names):
-            if v == 0:
+            if v == 0 or (modulus and B and not name.startswith("ring")):
                 continue
             try:
                 db.set_variant(B, v)
@@ -100,6 +107,8 @@ def main(argv=None) -> int:
     ap.add_argument("--batches", default="0,1,8,32,64,128,256,1024")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--modulus", type=int, default=0,
+                    help="time the field form mod this prime (Goldberg shapes)")
     args = ap.parse_args(argv)
     import torch
     import workload
@@ -110,7 +119,7 @@ def main(argv=None) -> int:
         D = workload.device_db(R, C, workload.SEED_BASE + 77, "cuda")
         with Database(D) as db:
             res = tune_database(db, batches, args.reps,
-                                log=lambda m: print(m, flush=True))
+                                log=lambda m: print(m, flush=True), modulus=args.modulus)
         entry = table.setdefault(f"{R}x{C}", {"best": {}, "us": {}})
         entry["best"].update(best(res))          # merge: other batch sizes keep their choice
         entry["us"].update({str(B): t for B, t in res.items()})
