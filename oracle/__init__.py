@@ -33,7 +33,13 @@ Contents
   i receives (f_1(alpha_i), ..., f_r(alpha_i)); the client interpolates the
   servers' responses at 0.  The random coefficients are inputs.
 
-Parity is pinned for every function here (see ``tests/test_oracle_pins.py``):
+* ``oracle.cip``: CIP-PIR, the OOP instantiation (Section 5.1, full
+  instantiation; proof of Lemma 2): chunk layout per server, ChaCha20 PRG,
+  offline seed/value pairs, online flip-chunk response, client queries and
+  reconstruction (see that module).
+
+Parity is pinned for every function here (see ``tests/test_oracle_pins.py``
+and ``tests/test_oracle_cip.py``):
 brute force on tiny inputs, closed forms, a hand-worked example, the LWE
 round trip and invariants.
 """
