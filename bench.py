@@ -7,8 +7,9 @@ one Answer over the resident database; inputs are in HBM before timing.
 
 Also reported on the same line: the 64-query batched Answer and the offline
 hint on the same database (matrix cores); a 16 GiB database (256-query batch,
-hint, 1% refresh with incremental hint); Chor XOR PIR and the Goldberg field
-form at 2^18 records of 3 KB; the serving loop (latency percentiles under
+hint, 1% refresh with incremental hint); Chor XOR PIR, the Goldberg field
+form and the CIP-PIR offline/online split at 2^18 records of 3 KB; the
+serving loop (latency percentiles under
 Poisson arrivals); and the oracle timed on the host cores on a bounded sample
 (``cpu_baseline``).
 
@@ -240,6 +241,55 @@ def ftr_bench(stream) -> dict:
     return res
 
 
+def oop_bench(stream) -> dict:
+    """CIP-PIR (the OOP instantiation) at the paper's largest database: 2^18
+    blocks of 3 KB in n = 4 chunks, every server holding all chunks (t = 4) in
+    its own order.  Online: one server's response over its flip chunk (1/4 of
+    the database) for 1, 2^7 and 2^10 queries, each XORed with its offline
+    value.  Offline: the values A for 2^10 seeds (ChaCha20 expansion plus the
+    XOR over the 3/4 non-flip part).  The paper's Table 2 reports 13.22 /
+    30.63 / 218.12 ms for its online GPU rows at this size (on another GPU,
+    including fixed overheads); context, not a target."""
+    import torch
+    import paper_2510_03631_amd as qp
+    import workload
+    dev = torch.device("cuda:0")
+    n, t = 4, 4
+    r, W = workload.CHOR_ROWS[-1], workload.CHOR_ENTRY_BYTES // 4
+    k = r // n
+    loc = workload.device_u32((t * k, W), workload.SEED_BASE + 90, dev)
+    res = {"workload": f"{r} blocks x {workload.CHOR_ENTRY_BYTES} B ({r * W * 4 / 2**20:.0f} MiB), "
+                       f"n = {n} chunks, t = {t}; flip chunk {k} blocks",
+           "paper_table2_gpu_ms": {"1": 13.22, "128": 30.63, "1024": 218.12}}
+    g = workload.rng(workload.SEED_BASE + 91)
+    Bmax = max(workload.CHOR_BATCHES)
+    seeds = torch.from_numpy(workload.uniform_u32(g, (Bmax, 8)).view("int32")).to(dev)
+    A = torch.empty((Bmax, W), dtype=torch.int32, device=dev)
+    ws = torch.empty(int(qp.lib().pir_oop_workspace_bytes(k, t, Bmax)), dtype=torch.uint8,
+                     device=dev)
+    fo = lambda: qp.oop_offline(loc, k, t, seeds, out=A, ws=ws)
+    fo()
+    _, evo = time_on_stream(fo, 3, stream)
+    to = evo / 3
+    res["offline_1024"] = {"ms": round(to * 1e3, 3),
+                           "nonflip_gbs": round((t - 1) * k * W * 4 / to / 1e9, 1),
+                           "values_per_s": round(Bmax / to, 1)}
+    for B in workload.CHOR_BATCHES:
+        Q = torch.from_numpy(workload.chor_query_words(g, k, B).view("int32")).to(dev)
+        out = torch.empty((B, W), dtype=torch.int32, device=dev)
+        fn = lambda: qp.oop_answer(loc, k, Q, A[:B], out=out)
+        fn()
+        reps = 10 if B < 1024 else 5
+        _, ev = time_on_stream(fn, reps, stream)
+        tq = ev / reps
+        res[f"B{B}"] = {"ms": round(tq * 1e3, 4),
+                        "flip_chunk_gbs": round(k * W * 4 / tq / 1e9, 1),
+                        "queries_per_s": round(B / tq, 1)}
+    del loc, A, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_run(srv, t_off, which, qs) -> dict:
     """Replay one open-loop trace; latency percentiles and throughput."""
     import numpy as np
@@ -382,6 +432,7 @@ def main() -> int:
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-chor", action="store_true")
     ap.add_argument("--no-ftr", action="store_true")
+    ap.add_argument("--no-oop", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--profile", choices=["answer", "batch", "hint", "calibrate"],
                     help="run only one kernel family (for rocprofv3 runs) and exit")
@@ -509,6 +560,13 @@ def main() -> int:
             db.close()
         torch.cuda.empty_cache()
         result["ftr"] = ftr_bench(stream)
+
+    if not args.no_oop:
+        log("CIP-PIR offline/online: 2^18 x 3 KB, n = t = 4, batches 1 / 128 / 1024")
+        if db._h is not None:
+            db.close()
+        torch.cuda.empty_cache()
+        result["oop"] = oop_bench(stream)
 
     if not args.no_serving:
         log("serving: 8 resident databases, Poisson arrivals, Zipf(1.1)")

@@ -8,6 +8,7 @@
  *   batch       Out = D Q        mod 2^32   (Q: C x B words)
  *   hint        H   = D A        mod 2^32   (A: C x n words, offline)
  *   field       Out = D Q        mod p      (Goldberg shares, p < 2^32)
+ *   xor         out = XOR of the rows a bit vector selects (Chor, CIP-PIR)
  *
  * This is the response step of the PIR interface (Definition 1: each
  * database server turns a query into a response derived from its local
@@ -253,6 +254,48 @@ pir_status pir_client_decode(const uint32_t* d_H, uint32_t R, uint32_t n, const 
 pir_status pir_chor_answer(const uint32_t* d_DB, uint32_t rows, uint32_t words,
                            uint64_t row_pitch_words, const uint32_t* d_Q, uint32_t B,
                            uint32_t* d_out, pir_stream_t stream);
+
+/*
+ * CIP-PIR, the OOP instantiation (Section 5.1: full instantiation; proof of
+ * Lemma 2).  The database's r blocks form n chunks of k blocks; server i
+ * stores t of them, chunk i (its flip chunk) first, then chunks i+1 ..
+ * i+t-1 mod n (non-flip).  A server's local database is therefore t*k rows
+ * of `words` 32-bit words (the layout of pir_chor_answer), rows 0 .. k-1
+ * being the flip chunk.
+ *
+ * pir_prg_expand: the PRG.  For each of `count` 8-word seeds, the first
+ *   `bits` bits of the ChaCha20 keystream (RFC 8439 block function; seed =
+ *   key, nonce 0, block counter from 0), as ceil(bits/32) words per seed
+ *   (keystream words in order, little endian; bits past `bits` cleared).
+ *     d_seeds  count x 8 words.   d_out  count x ceil(bits/32) words.
+ *
+ * pir_oop_offline: the client-independent precomputation.  For each seed e,
+ *   A[e] = XOR of the non-flip rows k + m (m < k(t-1)) whose bit m is set in
+ *   pir_prg_expand(seed e, k(t-1)).  t == 1 gives A = 0.
+ *     d_DB     the server's local database (t*k rows).
+ *     d_A      count x words.
+ *     d_ws     pir_oop_workspace_bytes(k, t, count) bytes, 256-byte aligned
+ *              (NULL allowed when that is 0): the expanded selector bits.
+ *
+ * pir_oop_answer: the online response.  For each query b,
+ *   out[b] = A[b] xor (XOR of the flip-chunk rows i < k whose bit i is set
+ *   in query b), with queries packed as for pir_chor_answer over k rows.
+ *     d_Q  B x ceil(k/32) words.   d_A, d_out  B x words (d_A[b] is the
+ *     offline value paired with query b's seed).
+ *
+ * count == 0 or B == 0 is a no-op.  Errors: PIR_ERR_INVALID_ARG (null
+ * pointer, bits == 0), PIR_ERR_SHAPE (zero or oversized sizes, pitch <
+ * words), PIR_ERR_WORKSPACE, PIR_ERR_UNSUPPORTED (device not gfx950).
+ */
+pir_status pir_prg_expand(const uint32_t* d_seeds, uint32_t count, uint32_t bits,
+                          uint32_t* d_out, pir_stream_t stream);
+size_t pir_oop_workspace_bytes(uint32_t k, uint32_t t, uint32_t count);
+pir_status pir_oop_offline(const uint32_t* d_DB, uint32_t k, uint32_t t, uint32_t words,
+                           uint64_t row_pitch_words, const uint32_t* d_seeds, uint32_t count,
+                           uint32_t* d_A, void* d_ws, size_t ws_bytes, pir_stream_t stream);
+pir_status pir_oop_answer(const uint32_t* d_DB, uint32_t k, uint32_t words,
+                          uint64_t row_pitch_words, const uint32_t* d_Q, uint32_t B,
+                          const uint32_t* d_A, uint32_t* d_out, pir_stream_t stream);
 
 /*
  * Kernel variants (tile shapes, pipeline depths, rows per wave) for the

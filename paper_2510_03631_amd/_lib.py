@@ -81,6 +81,10 @@ SIGNATURES = {
     "pir_client_query": (_ST, [_P, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
     "pir_client_decode": (_ST, [_P, _U32, _U32, _P, _P, _U32, _P, _P]),
     "pir_chor_answer": (_ST, [_P, _U32, _U32, _U64, _P, _U32, _P, _P]),
+    "pir_prg_expand": (_ST, [_P, _U32, _U32, _P, _P]),
+    "pir_oop_workspace_bytes": (_SZ, [_U32, _U32, _U32]),
+    "pir_oop_offline": (_ST, [_P, _U32, _U32, _U32, _U64, _P, _U32, _P, _P, _SZ, _P]),
+    "pir_oop_answer": (_ST, [_P, _U32, _U32, _U64, _P, _U32, _P, _P, _P]),
 }
 
 
@@ -400,4 +404,74 @@ def chor_answer(DB: torch.Tensor, Q: torch.Tensor, out: torch.Tensor = None,
     with torch.cuda.device(dev):
         check(lib().pir_chor_answer(DB.data_ptr(), rows, W, pitch, qp_, B, op,
                                     _stream_ptr(stream, dev)), "pir_chor_answer")
+    return out
+
+
+def _word_matrix(DB: torch.Tensor, name: str):
+    if DB.dim() != 2 or DB.stride(1) != 1 or DB.dtype not in _WORD:
+        raise ValueError(f"{name} must be a 2-D 32-bit word tensor with unit column stride")
+    if not DB.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    rows, W = int(DB.shape[0]), int(DB.shape[1])
+    return rows, W, (int(DB.stride(0)) if rows > 1 else W)
+
+
+def prg_expand(seeds: torch.Tensor, bits: int, out: torch.Tensor = None,
+               stream=None) -> torch.Tensor:
+    """ChaCha20 expansion of ``count`` 8-word seeds into ``bits`` bits each
+    (``pir_prg_expand``); returns count x ceil(bits/32) words."""
+    count = int(seeds.shape[0])
+    dev = seeds.device
+    sp = _ptr_words(seeds, "seeds", (count, 8), dev)
+    nw = (int(bits) + 31) // 32
+    if out is None:
+        out = torch.empty((count, nw), dtype=torch.int32, device=dev)
+    op = _ptr_words(out, "out", (count, nw), dev)
+    with torch.cuda.device(dev):
+        check(lib().pir_prg_expand(sp, count, int(bits), op, _stream_ptr(stream, dev)),
+              "pir_prg_expand")
+    return out
+
+
+def oop_offline(local: torch.Tensor, k: int, t: int, seeds: torch.Tensor,
+                out: torch.Tensor = None, ws: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Offline values A (count x W) of a server's local database (t*k x W
+    words, flip chunk first) for ``count`` seeds (``pir_oop_offline``)."""
+    rows, W, pitch = _word_matrix(local, "local")
+    if rows != int(k) * int(t):
+        raise ValueError("local must hold t * k rows")
+    count = int(seeds.shape[0])
+    dev = local.device
+    sp = _ptr_words(seeds, "seeds", (count, 8), dev)
+    if out is None:
+        out = torch.empty((count, W), dtype=torch.int32, device=dev)
+    op = _ptr_words(out, "out", (count, W), dev)
+    nbytes = int(lib().pir_oop_workspace_bytes(int(k), int(t), count))
+    if ws is None and nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    wp = ws.data_ptr() if ws is not None else None
+    wn = ws.numel() * ws.element_size() if ws is not None else 0
+    with torch.cuda.device(dev):
+        check(lib().pir_oop_offline(local.data_ptr(), int(k), int(t), W, pitch, sp, count, op,
+                                    wp, wn, _stream_ptr(stream, dev)), "pir_oop_offline")
+    return out
+
+
+def oop_answer(local: torch.Tensor, k: int, Q: torch.Tensor, A: torch.Tensor,
+               out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Online responses (B x W): ``A[b]`` xor the flip-chunk rows (the first
+    ``k`` rows of ``local``) selected by query ``Q[b]`` (``pir_oop_answer``)."""
+    rows, W, pitch = _word_matrix(local, "local")
+    if rows < int(k):
+        raise ValueError("local must hold at least k rows")
+    B = int(Q.shape[0])
+    dev = local.device
+    qp_ = _ptr_words(Q, "Q", (B, (int(k) + 31) // 32), dev)
+    ap = _ptr_words(A, "A", (B, W), dev)
+    if out is None:
+        out = torch.empty((B, W), dtype=torch.int32, device=dev)
+    op = _ptr_words(out, "out", (B, W), dev)
+    with torch.cuda.device(dev):
+        check(lib().pir_oop_answer(local.data_ptr(), int(k), W, pitch, qp_, B, ap, op,
+                                   _stream_ptr(stream, dev)), "pir_oop_answer")
     return out

@@ -33,9 +33,12 @@ namespace {
 constexpr int kThreads = 256;
 constexpr uint32_t kChunkWords = 4 * kThreads;
 
-__global__ void k_chor_zero(uint32_t* __restrict__ p, uint64_t n) {
+// Output before accumulation: zero, or a copy of `init` (the OOP response
+// starts from its precomputed value A).
+__global__ void k_chor_init(uint32_t* __restrict__ p, const uint32_t* __restrict__ init,
+                            uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
+    if (i < n) p[i] = init ? init[i] : 0u;
 }
 
 template <bool VEC>
@@ -188,6 +191,8 @@ pir_status launch_chor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint
     return PIR_OK;
 }
 
+}  // namespace
+
 bool current_is_gfx950() {
     int dev = -1;
     hipDeviceProp_t prop;
@@ -196,7 +201,26 @@ bool current_is_gfx950() {
     return strncmp(prop.gcnArchName, "gfx950", 6) == 0;
 }
 
-}  // namespace
+pir_status chor_init(uint32_t* d_out, const uint32_t* d_init, uint64_t n, hipStream_t s) {
+    if (n == 0) return PIR_OK;
+    if ((n + 255) / 256 > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    k_chor_init<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(d_out, d_init, n);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
+pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
+                    const uint32_t* d_Q, uint32_t B, const uint32_t* d_init, uint32_t* d_out,
+                    hipStream_t s) {
+    const pir_status st = chor_init(d_out, d_init, (uint64_t)B * words, s);
+    if (st != PIR_OK) return st;
+    // Small batches stream every row under masks; larger ones use the
+    // 4-row tables.  Fewer, longer slabs for large batches keep the number of
+    // output atomics down.
+    if (B <= 4) return launch_chor<4, false>(d_DB, rows, words, pitch, d_Q, B, d_out, 2048, s);
+    if (B <= 64) return launch_chor<16, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 2048, s);
+    return launch_chor<32, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
+}
 
 extern "C" {
 
@@ -209,16 +233,8 @@ pir_status pir_chor_answer(const uint32_t* d_DB, uint32_t rows, uint32_t words,
         words > kMaxDim || B > kMaxBatch)
         return PIR_ERR_SHAPE;
     if (!current_is_gfx950()) return PIR_ERR_UNSUPPORTED;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t n_out = (uint64_t)B * words;
-    k_chor_zero<<<(uint32_t)((n_out + 255) / 256), 256, 0, s>>>(d_out, n_out);
-    PIR_LAUNCH_CHECK();
-    // Small batches stream every row under masks; larger ones use the
-    // 4-row tables.  Fewer, longer slabs for large batches keep the number of
-    // output atomics down.
-    if (B <= 4) return launch_chor<4, false>(d_DB, rows, words, row_pitch_words, d_Q, B, d_out, 2048, s);
-    if (B <= 64) return launch_chor<16, true>(d_DB, rows, words, row_pitch_words, d_Q, B, d_out, 2048, s);
-    return launch_chor<32, true>(d_DB, rows, words, row_pitch_words, d_Q, B, d_out, 512, s);
+    return chor_xor(d_DB, rows, words, row_pitch_words, d_Q, B, nullptr, d_out,
+                    static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

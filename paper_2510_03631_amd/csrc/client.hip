@@ -93,14 +93,6 @@ __global__ __launch_bounds__(64 * kCWaves) void k_rowdot(
     }
 }
 
-bool current_is_gfx950() {
-    int dev = -1;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return false;
-    return strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-}
-
 uint32_t grid_for(uint32_t rows) {
     const uint32_t blocks = (rows + kCWaves - 1) / kCWaves;
     return blocks < 16384 ? blocks : 16384;

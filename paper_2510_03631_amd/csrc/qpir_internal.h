@@ -82,3 +82,13 @@ size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B);
 pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
                              const uint32_t* rows, uint32_t m, uint32_t modulus, void* ws,
                              size_t ws_bytes, hipStream_t s);
+
+// ---- XOR (Chor) path (chor.hip)
+bool current_is_gfx950();
+// out[i] = init[i] (or 0) for i < n (a fill kernel: safe under graph capture).
+pir_status chor_init(uint32_t* d_out, const uint32_t* d_init, uint64_t n, hipStream_t s);
+// out[b] = init[b] (or 0) xor XOR of the rows of DB selected by query b.
+// Arguments already checked by the caller.
+pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
+                    const uint32_t* d_Q, uint32_t B, const uint32_t* d_init, uint32_t* d_out,
+                    hipStream_t s);
