@@ -393,6 +393,8 @@ def profile_mode(args, dev, stream) -> int:
                           "copy_us": round(t * 1e6, 2),
                           "copy_gbs_read_plus_write": round(2 * x.numel() * 4 / t / 1e9, 1)}))
         return 0
+    if args.profile.startswith(("chor", "oop", "ftr")):
+        return profile_instantiation(args, dev, stream)
     D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
     db = qp.Database(D)
     tune.apply(db)
@@ -421,6 +423,45 @@ def profile_mode(args, dev, stream) -> int:
     return 0
 
 
+def profile_instantiation(args, dev, stream) -> int:
+    """``chorB``, ``oopB`` (online) and ``ftrB`` profile modes: the 2^18 x 3 KB
+    workloads of the instantiation legs with B queries."""
+    import re
+    import torch
+    import paper_2510_03631_amd as qp
+    from paper_2510_03631_amd import tune
+    import workload
+    kind, B = re.fullmatch(r"(chor|oop|ftr)(\d+)", args.profile).groups()
+    B = int(B)
+    rows, W = workload.CHOR_ROWS[-1], workload.CHOR_ENTRY_BYTES // 4
+    g = workload.rng(workload.SEED_BASE + 95)
+    if kind == "ftr":
+        R, C, p = workload.FTR_RECORD_BYTES, workload.FTR_RECORDS[-1], workload.FTR_PRIME
+        D = workload.device_db(R, C, workload.SEED_BASE + 70, dev)
+        db = qp.Database(D)
+        tune.apply(db)
+        Q = workload.device_mod((C, B), p, workload.SEED_BASE + 71 + B, dev)
+        out = torch.empty((R, B), dtype=torch.int32, device=dev)
+        ws = db.workspace(B)
+        fn = lambda: db.answer_batch_modp(Q, p, out=out, ws=ws)
+    else:
+        k = rows // 4 if kind == "oop" else rows
+        DB = workload.device_u32((rows, W), workload.SEED_BASE + 60, dev)
+        Q = torch.from_numpy(workload.chor_query_words(g, k, B).view("int32")).to(dev)
+        out = torch.empty((B, W), dtype=torch.int32, device=dev)
+        if kind == "chor":
+            fn = lambda: qp.chor_answer(DB, Q, out=out)
+        else:
+            A = workload.device_u32((B, W), workload.SEED_BASE + 96, dev)
+            fn = lambda: qp.oop_answer(DB, k, Q, A, out=out)
+    for _ in range(args.warmup):
+        fn()
+    wall, ev = time_on_stream(fn, args.steps, stream)
+    print(json.dumps({"profile": args.profile, "steps": args.steps,
+                      "avg_us": round(ev / args.steps * 1e6, 2)}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,8 +475,9 @@ def main() -> int:
     ap.add_argument("--no-ftr", action="store_true")
     ap.add_argument("--no-oop", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
-    ap.add_argument("--profile", choices=["answer", "batch", "hint", "calibrate"],
-                    help="run only one kernel family (for rocprofv3 runs) and exit")
+    ap.add_argument("--profile",
+                    help="run only one kernel family (for rocprofv3 runs) and exit: answer, "
+                         "batch, hint, calibrate, or chorB / oopB / ftrB with B queries")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",

@@ -15,10 +15,14 @@
 // * per 32-row block the group's selector words are loaded once (lane g
 //   holds query g's word; wave-uniform reads pick bits out), and rows are
 //   loaded 8 at a time, back to back;
-// * batches of at most 4 queries XOR every row under a wave-uniform mask;
-//   larger batches build, per 4 rows, the 16 XOR combinations of the rows
-//   in a wave-private LDS table and add one table entry per query (method
-//   of the Four Russians): one LDS read and XOR per query per 4 rows;
+// * batches of at most 4 queries (k_chor_stream) read only the rows that
+//   some query selects (a single query touches half of the database): the
+//   selector words of a whole slab are fetched up front, set bits are taken
+//   with a wave-uniform bit scan, and up to 16 rows per wave are in flight
+//   (non-temporal loads); each row is XORed into every query under a mask;
+// * larger batches (k_chor) build, per 4 rows, the 16 XOR combinations of
+//   the rows in a wave-private LDS table and add one table entry per query
+//   (method of the Four Russians): one LDS read and XOR per query per 4 rows;
 // * workgroups are numbered slab-major and dealt to XCDs in contiguous
 //   ranges, so the query groups of one slab share its rows in L2;
 // * slabs combine into the output with atomicXor (XOR is associative and
@@ -46,6 +50,109 @@ __device__ inline u32x4 load_words(const uint32_t* row, uint32_t w, uint32_t W) 
     if (VEC) return *reinterpret_cast<const u32x4*>(row + w);   // W % 4 == 0, aligned
     return u32x4{w < W ? row[w] : 0u, w + 1 < W ? row[w + 1] : 0u,
                  w + 2 < W ? row[w + 2] : 0u, w + 3 < W ? row[w + 3] : 0u};
+}
+
+template <bool VEC>
+__device__ inline u32x4 load_words_nt(const uint32_t* row, uint32_t w, uint32_t W) {
+    if (VEC) return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row + w));
+    return load_words<false>(row, w, W);
+}
+
+__device__ inline uint32_t xcd_remap(uint32_t bid, uint32_t nblk) {
+    const uint32_t per = nblk / 8u;
+    return bid < per * 8u ? (bid % 8u) * per + bid / 8u : bid;
+}
+
+// Batches of at most G queries (G * 16 <= 64).  Workgroup = one slab of rows
+// [r0, r1), all columns in chunks of 1024 words (lane t: words 4t..4t+3).
+// One load per lane fetches the selector words of 64 / G consecutive 32-row
+// blocks (lane l: query l / (64/G), block l % (64/G)); per block the OR of the
+// queries' words names the rows to read, taken kDepth at a time.
+constexpr int kDepth = 16;
+
+template <int G, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_chor_stream(const uint32_t* __restrict__ DB,
+                                                          uint64_t pitch, uint32_t rows,
+                                                          uint32_t W,
+                                                          const uint32_t* __restrict__ Q,
+                                                          uint32_t qwords, uint32_t B,
+                                                          uint32_t slab_rows,
+                                                          uint32_t* __restrict__ out) {
+    constexpr uint32_t kBlocks = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t slab = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t r0 = slab * slab_rows;
+    const uint32_t r1 = min(rows, r0 + slab_rows);
+
+    for (uint32_t c0 = 0; c0 < W; c0 += kChunkWords) {
+        if (c0 + 256u * (uint32_t)wave >= W) continue;   // no lane of this wave has words here
+        const uint32_t w = c0 + 4u * threadIdx.x;
+        const bool active = w < W;
+        u32x4 acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = u32x4{0, 0, 0, 0};
+
+        for (uint32_t base = r0; base < r1; base += 32u * kBlocks) {
+            uint32_t qv = 0;
+            {
+                const uint32_t g = (uint32_t)lane / kBlocks;
+                const uint32_t rb = base + 32u * ((uint32_t)lane % kBlocks);
+                if (g < B && rb < r1) {
+                    qv = Q[(uint64_t)g * qwords + rb / 32u];
+                    const uint32_t nrow = min(32u, r1 - rb);
+                    if (nrow < 32u) qv &= (1u << nrow) - 1u;
+                }
+            }
+            for (uint32_t jb = 0; jb < kBlocks; ++jb) {
+                const uint32_t rblk = base + 32u * jb;
+                if (rblk >= r1) break;                    // uniform
+                uint32_t sel[G];
+                uint32_t any = 0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    sel[g] = __builtin_amdgcn_readlane(qv, g * (int)kBlocks + (int)jb);
+                    any |= sel[g];
+                }
+                while (any) {
+                    uint32_t idx[kDepth];
+                    u32x4 d[kDepth];
+#pragma unroll
+                    for (int k = 0; k < kDepth; ++k) {
+                        idx[k] = 0;
+                        d[k] = u32x4{0, 0, 0, 0};
+                        if (any) {                        // uniform
+                            idx[k] = (uint32_t)__builtin_ctz(any);
+                            any &= any - 1u;
+                            if (active)
+                                d[k] = load_words_nt<VEC>(DB + (uint64_t)(rblk + idx[k]) * pitch,
+                                                          w, W);
+                        }
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+#pragma unroll
+                        for (int k = 0; k < kDepth; ++k) {
+                            const uint32_t m = 0u - ((sel[g] >> idx[k]) & 1u);
+                            acc[g] ^= d[k] & u32x4{m, m, m, m};
+                        }
+                    }
+                }
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if ((uint32_t)g < B) {
+                    uint32_t* o = out + (uint64_t)g * W + w;
+                    if (acc[g].x) atomicXor(o, acc[g].x);
+                    if (w + 1 < W && acc[g].y) atomicXor(o + 1, acc[g].y);
+                    if (w + 2 < W && acc[g].z) atomicXor(o + 2, acc[g].z);
+                    if (w + 3 < W && acc[g].w) atomicXor(o + 3, acc[g].w);
+                }
+            }
+        }
+    }
 }
 
 // Work of one workgroup: rows [r0, r1) of a slab, queries [b0, b0 + nb) of a
@@ -82,6 +189,10 @@ __global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ 
     if (TABLE) tab[lane] = u32x4{0, 0, 0, 0};   // entry 0: no row selected
 
     for (uint32_t c0 = 0; c0 < W; c0 += kChunkWords) {
+        // A wave whose 64 lanes all lie past the last word has nothing to do
+        // in this chunk (3 KB blocks leave the fourth wave idle); the waves
+        // never synchronize with each other, so it moves on.
+        if (c0 + 256u * (uint32_t)wave >= W) continue;
         const uint32_t w = c0 + 4u * threadIdx.x;
         const bool active = w < W;
         u32x4 acc[G];
@@ -135,19 +246,16 @@ __global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ 
                         tab[13 * 64 + lane] = x3 ^ t5;
                         tab[14 * 64 + lane] = x3 ^ t6;
                         tab[15 * 64 + lane] = x3 ^ t7;
-                        // The table is private to the wave and LDS accesses of a
-                        // wave complete in order; keep the compiler from moving
-                        // the reads above the writes.
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        // Each lane reads only its own column of the table
+                        // (entry * 64 + lane), so the table is per-lane data:
+                        // program order alone orders these reads after the
+                        // writes above and before the next writes.
                         const int sh = s8 + 4 * h;
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
                             const uint32_t idx = (__builtin_amdgcn_readlane(qv, g) >> sh) & 15u;
                             acc[g] ^= tab[idx * 64 + lane];
                         }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     }
                 }
                 if ((uint32_t)(s8 + 8) >= nrow) break;
@@ -156,12 +264,13 @@ __global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ 
         if (active) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                if ((uint32_t)g >= nb) break;
-                uint32_t* o = out + (uint64_t)(b0 + g) * W + w;
-                const uint32_t v[4] = {acc[g].x, acc[g].y, acc[g].z, acc[g].w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (w + e < W && v[e]) atomicXor(o + e, v[e]);
+                if ((uint32_t)g < nb) {
+                    uint32_t* o = out + (uint64_t)(b0 + g) * W + w;
+                    if (acc[g].x) atomicXor(o, acc[g].x);
+                    if (w + 1 < W && acc[g].y) atomicXor(o + 1, acc[g].y);
+                    if (w + 2 < W && acc[g].z) atomicXor(o + 2, acc[g].z);
+                    if (w + 3 < W && acc[g].w) atomicXor(o + 3, acc[g].w);
+                }
             }
         }
     }
@@ -187,6 +296,30 @@ pir_status launch_chor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint
     else
         k_chor<G, TABLE, false><<<(uint32_t)blocks, kThreads, lds, s>>>(
             d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_groups, d_out);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
+pir_status launch_stream(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
+                         const uint32_t* d_Q, uint32_t B, uint32_t* d_out, hipStream_t s) {
+    constexpr int G = 4;
+    const uint32_t qwords = (rows + 31) / 32;
+    // About two workgroups per CU: enough rows in flight to stream HBM, few
+    // enough slabs to keep the output atomics (slabs x B x words) down.
+    uint64_t slab = (rows + 511u) / 512u;
+    slab = (slab + 31) / 32 * 32;
+    if (slab < 32) slab = 32;
+    const uint64_t blocks = (rows + slab - 1) / slab;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    const bool vec = ((uintptr_t)d_DB % 16 == 0) && (words % 4 == 0) && (pitch % 4 == 0);
+    if (vec)
+        k_chor_stream<G, true><<<(uint32_t)blocks, kThreads, 0, s>>>(d_DB, pitch, rows, words, d_Q,
+                                                                     qwords, B, (uint32_t)slab,
+                                                                     d_out);
+    else
+        k_chor_stream<G, false><<<(uint32_t)blocks, kThreads, 0, s>>>(d_DB, pitch, rows, words, d_Q,
+                                                                      qwords, B, (uint32_t)slab,
+                                                                      d_out);
     PIR_LAUNCH_CHECK();
     return PIR_OK;
 }
@@ -217,8 +350,8 @@ pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_
     // Small batches stream every row under masks; larger ones use the
     // 4-row tables.  Fewer, longer slabs for large batches keep the number of
     // output atomics down.
-    if (B <= 4) return launch_chor<4, false>(d_DB, rows, words, pitch, d_Q, B, d_out, 2048, s);
-    if (B <= 64) return launch_chor<16, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 2048, s);
+    if (B <= 4) return launch_stream(d_DB, rows, words, pitch, d_Q, B, d_out, s);
+    if (B <= 64) return launch_chor<16, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
     return launch_chor<32, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
 }
 
