@@ -856,6 +856,7 @@ using Ring128x256S6 = Ring<2, 2, 2, 4, 6>;              // 144 KiB
 using Ring8w128x256K128S3 = Ring<4, 2, 1, 4, 3, 128>;   // 8 waves, 144 KiB
 using Ring8w256x256S4 = Ring<4, 2, 2, 4, 4>;            // 8 waves, 128 KiB
 using Ring8w256x256K128S2 = Ring<4, 2, 2, 4, 2, 128>;   // 8 waves, 128 KiB
+using Ring256x256K128S2 = Ring<2, 2, 4, 4, 2, 128>;     // 4 waves of 128 x 128, 128 KiB
 using Roles256x256A5B4 = Roles<2, 2, 4, 4, 5, 4>;       // 80 + 64 KiB
 using Roles128x256A10B4 = Roles<2, 2, 2, 4, 10, 4>;     // 80 + 64 KiB
 using Reg128x256 = Tile<2, 2, 2, 4, 128>;
@@ -878,14 +879,15 @@ const VariantInfo kVariants[] = {
     {"ring8w_128x256_k128_s3", kRing, 128, 256, 128, launch_ring<Ring8w128x256K128S3>},
     {"ring8w_256x256_s4", kRing, 256, 256, 64, launch_ring<Ring8w256x256S4>},
     {"ring8w_256x256_k128_s2", kRing, 256, 256, 128, launch_ring<Ring8w256x256K128S2>},
+    {"ring_256x256_k128_s2", kRing, 256, 256, 128, launch_ring<Ring256x256K128S2>},
     {"roles_256x256_a5b4", kRoles, 256, 256, 64, launch_roles<Roles256x256A5B4>},
     {"roles_128x256_a10b4", kRoles, 128, 256, 64, launch_roles<Roles128x256A10B4>},
     {"reg_128x256", kReg, 128, 256, 128, launch_reg<Reg128x256>},
     {"reg_128x128", kReg, 128, 128, 128, launch_reg<Reg128x128>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 9,
-                   kVarReg128 = 10;
+constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
+                   kVarReg128 = 11;
 
 bool ring_ok(const pir_db_t* db) { return db->aligned && (db->cols % 16 == 0); }
 
@@ -1016,6 +1018,7 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Ring8w128x256K128S3>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring8w256x256S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring8w256x256K128S2>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring256x256K128S2>()) != PIR_OK) return st;
     if ((st = set_roles_lds<Roles256x256A5B4>()) != PIR_OK) return st;
     return set_roles_lds<Roles128x256A10B4>();
 }

@@ -250,11 +250,20 @@ __global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ 
                         // (entry * 64 + lane), so the table is per-lane data:
                         // program order alone orders these reads after the
                         // writes above and before the next writes.
+                        // Lookups in batches of 8: the reads are issued together
+                        // so that several are in flight before the XORs wait.
                         const int sh = s8 + 4 * h;
 #pragma unroll
-                        for (int g = 0; g < G; ++g) {
-                            const uint32_t idx = (__builtin_amdgcn_readlane(qv, g) >> sh) & 15u;
-                            acc[g] ^= tab[idx * 64 + lane];
+                        for (int g0 = 0; g0 < G; g0 += 8) {
+                            u32x4 t[8];
+#pragma unroll
+                            for (int g = 0; g < 8; ++g) {
+                                const uint32_t idx =
+                                    (__builtin_amdgcn_readlane(qv, g0 + g) >> sh) & 15u;
+                                t[g] = tab[idx * 64 + lane];
+                            }
+#pragma unroll
+                            for (int g = 0; g < 8; ++g) acc[g0 + g] ^= t[g];
                         }
                     }
                 }
