@@ -50,7 +50,10 @@
 //
 // QL row index of (query b, limb k): n = (b / 32) * 128 + k * 32 + (b % 32),
 // so the four limbs of a query land in the same lane of four adjacent 32x32
-// output tiles and the epilogue combines them in registers.
+// output tiles and the epilogue combines them in registers.  QL is stored in
+// 4 KiB tiles of 32 rows x 128 bytes (tile (n/32, k/128) at
+// ((n/32) * Cp/128 + k/128) * 4096, row n%32 at 128 (n%32) within it): the
+// ingest writes whole tiles and a 1 KiB block of a GEMM k-tile is contiguous.
 #include "qpir_internal.h"
 
 namespace {
@@ -67,6 +70,12 @@ constexpr uint32_t kExactSpan = 1u << 17;     // columns one exact int32 accumul
 constexpr uint32_t kMaxExactCols = 1u << 23;  // D q < 2^64 and exact row sums
 constexpr uint32_t kMaxSplits = 16;           // split-K pieces chosen for occupancy
 
+// Byte offset of QL element (n, 0) and the offset added for column k.
+__device__ inline uint64_t ql_row(uint32_t n, uint32_t Cp) {
+    return (uint64_t)(n / 32u) * 32u * Cp + (uint64_t)(n % 32u) * 128u;
+}
+__device__ inline uint32_t ql_col(uint32_t k) { return (k >> 7) * 4096u + (k & 127u); }
+
 // Epilogue modes.
 enum : int {
     kFinal32 = 0,     // Out mod 2^32
@@ -80,68 +89,119 @@ __global__ void k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
     if (i < n) p[i] = 0;
 }
 
-// Block: 64 query coordinates j x 32 queries b.  Element (j, b) of the
-// query matrix is Q[j * ldj + b * ldb].  The load is coalesced along b for
-// the row-major layout (ldb == 1) and along j for the query-major one
-// (QMAJOR, ldj == 1); both go through an LDS tile, then each thread writes
-// 32 limb bytes of one query and the limb-0 threads add the exact column
-// sums.
-template <bool QMAJOR>
+// Block: 128 query coordinates j x 64 queries b.  Element (j, b) of the
+// query matrix is Q[j * ldj + b * ldb].  Loads are coalesced along b for the
+// row-major layout (ldb == 1: a wave reads 64 consecutive words of one row)
+// and along j for the query-major one (QMAJOR, ldj == 1).  The tile goes
+// through LDS with rows padded to 129 words, so that both the store (64
+// lanes, one j, consecutive b) and the transposed read (64 lanes, consecutive
+// b, one j) hit 64 distinct banks.  Then thread (b, limb) writes the 128
+// limb bytes of its QL row as eight 16-byte stores (one full 128-byte run
+// per row), and the limb-0 threads add the exact column sums.
+constexpr int kIngJ = 128;
+constexpr int kIngB = 64;
+
+// VEC: 16-byte loads (4 consecutive queries of a row, or 4 consecutive
+// coordinates of a query), when the query matrix is 16-byte aligned and the
+// contiguous extent (B, or C for QMAJOR) is a multiple of 4; each thread then
+// has its whole share of the tile (8 loads, 128 bytes) in flight at once.
+template <bool QMAJOR, bool VEC>
 __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, uint64_t ldj,
-                                                uint64_t ldb, uint32_t C, uint32_t B, uint32_t Cp,
-                                                int8_t* __restrict__ QL, u64* __restrict__ colsum) {
-    __shared__ uint32_t s[32][65];
+                                                uint64_t ldb, uint32_t C, uint32_t B, uint32_t Bp,
+                                                uint32_t Cp, int8_t* __restrict__ QL,
+                                                u64* __restrict__ colsum) {
+    __shared__ uint32_t s[kIngB][kIngJ + 1];
     const int t = threadIdx.x;
-    const uint32_t j0 = blockIdx.x * 64u;
-    const uint32_t b0 = blockIdx.y * 32u;
-    if (QMAJOR) {
-        const int bb = t >> 3;
-        const uint32_t b = b0 + bb;
+    // Query blocks vary fastest across the grid, so the blocks that read one
+    // row of a row-major Q (64 queries each) are dispatched together.
+    const uint32_t b0 = blockIdx.x * (uint32_t)kIngB;
+    const uint32_t j0 = blockIdx.y * (uint32_t)kIngJ;
+    if (VEC && QMAJOR) {
+        const int j4 = t & 31, br = t >> 5;
+        const uint32_t j = j0 + 4u * j4;
+        u32x4 v[8];
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            const int jj = (t & 7) * 8 + p;
-            const uint32_t j = j0 + jj;
-            s[bb][jj] = (j < C && b < B) ? Q[(uint64_t)j * ldj + (uint64_t)b * ldb] : 0u;
+            const uint32_t b = b0 + br + 8 * p;
+            v[p] = (j < C && b < B)
+                       ? *reinterpret_cast<const u32x4*>(Q + (uint64_t)b * ldb + j)
+                       : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int bl = br + 8 * p;
+            s[bl][4 * j4 + 0] = v[p].x;
+            s[bl][4 * j4 + 1] = v[p].y;
+            s[bl][4 * j4 + 2] = v[p].z;
+            s[bl][4 * j4 + 3] = v[p].w;
+        }
+    } else if (VEC) {
+        const int q4 = t & 15, jr = t >> 4;
+        const uint32_t b = b0 + 4u * q4;
+        u32x4 v[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t j = j0 + jr + 16 * p;
+            v[p] = (j < C && b < B)
+                       ? *reinterpret_cast<const u32x4*>(Q + (uint64_t)j * ldj + b)
+                       : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int jl = jr + 16 * p;
+            s[4 * q4 + 0][jl] = v[p].x;
+            s[4 * q4 + 1][jl] = v[p].y;
+            s[4 * q4 + 2][jl] = v[p].z;
+            s[4 * q4 + 3][jl] = v[p].w;
+        }
+    } else if (QMAJOR) {
+        const int jl = t & (kIngJ - 1);
+        const uint32_t j = j0 + jl;
+#pragma unroll 8
+        for (int p = 0; p < kIngB / 2; ++p) {
+            const int bl = (t >> 7) + 2 * p;
+            const uint32_t b = b0 + bl;
+            s[bl][jl] = (j < C && b < B) ? Q[(uint64_t)j * ldj + (uint64_t)b * ldb] : 0u;
         }
     } else {
-        const int bb = t & 31;
-        const uint32_t b = b0 + bb;
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int jj = (t >> 5) + 8 * p;
-            const uint32_t j = j0 + jj;
-            s[bb][jj] = (j < C && b < B) ? Q[(uint64_t)j * ldj + (uint64_t)b * ldb] : 0u;
+        const int bl = t & (kIngB - 1);
+        const uint32_t b = b0 + bl;
+#pragma unroll 8
+        for (int p = 0; p < kIngJ / 4; ++p) {
+            const int jl = (t >> 6) + 4 * p;
+            const uint32_t j = j0 + jl;
+            s[bl][jl] = (j < C && b < B) ? Q[(uint64_t)j * ldj + (uint64_t)b * ldb] : 0u;
         }
     }
     __syncthreads();
+    const int bl = t & (kIngB - 1);
     const int limb = t >> 6;
-    const int bb = (t >> 1) & 31;
-    const int half = t & 1;
-    const uint32_t b = b0 + bb;
-    uint32_t w[8];
+    const uint32_t b = b0 + bl;
+    if (b >= Bp) return;                       // no QL row (one 32-query group only)
+    const bool live = b < B;
+    const uint32_t n = (b / 32u) * 128u + (uint32_t)limb * 32u + (b % 32u);
+    u32x4* dst = reinterpret_cast<u32x4*>(QL + ql_row(n, Cp) + ql_col(j0));
     u64 sum = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        uint32_t word = 0;
+#pragma unroll 2
+    for (int e = 0; e < kIngJ / 16; ++e) {
+        uint32_t w[4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-            const int jj = 32 * half + 4 * e + x;
-            const uint32_t j = j0 + jj;
-            const uint32_t v = s[bb][jj];
-            sum += v;
-            const uint32_t byte = (j < C && b < B) ? (((v >> (8 * limb)) & 0xFFu) ^ 0x80u) : 0u;
-            word |= byte << (8 * x);
+            uint32_t word = 0;
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int jl = 16 * e + 4 * x + y;
+                const uint32_t v = s[bl][jl];
+                sum += v;
+                const uint32_t byte =
+                    (live && j0 + jl < C) ? (((v >> (8 * limb)) & 0xFFu) ^ 0x80u) : 0u;
+                word |= byte << (8 * y);
+            }
+            w[x] = word;
         }
-        w[e] = word;
+        dst[e] = u32x4{w[0], w[1], w[2], w[3]};
     }
-    const uint32_t n = (b0 / 32u) * 128u + (uint32_t)limb * 32u + (uint32_t)bb;
-    u32x4* dst = reinterpret_cast<u32x4*>(QL + (uint64_t)n * Cp + j0 + 32u * half);
-    dst[0] = u32x4{w[0], w[1], w[2], w[3]};
-    dst[1] = u32x4{w[4], w[5], w[6], w[7]};
-    if (limb == 0) {
-        sum += __shfl_xor(sum, 1);
-        if (half == 0 && b < B) atomicAdd(&colsum[b], sum);
-    }
+    if (limb == 0 && live) atomicAdd(&colsum[b], sum);
 }
 
 // ---------------------------------------------------------------- epilogue
@@ -335,7 +395,7 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
     const int8_t* brow[T::B_LOADS];
 #pragma unroll
     for (int p = 0; p < T::B_LOADS; ++p)
-        brow[p] = QL + (uint64_t)(n0 + rsub + p * ROWS_PER_PASS) * Cp;
+        brow[p] = QL + ql_row(n0 + rsub + p * ROWS_PER_PASS, Cp);
 
     u32x4 ra[T::A_LOADS], rb[T::B_LOADS];
     auto gload = [&](uint32_t k0) {
@@ -344,7 +404,7 @@ __global__ __launch_bounds__(256) void k_gemm(const uint8_t* __restrict__ D, uin
         for (int p = 0; p < T::A_LOADS; ++p) ra[p] = load_row16<VEC>(arow[p], k, C);
 #pragma unroll
         for (int p = 0; p < T::B_LOADS; ++p)
-            rb[p] = *reinterpret_cast<const u32x4*>(brow[p] + k);
+            rb[p] = *reinterpret_cast<const u32x4*>(brow[p] + ql_col(k));
     };
     auto lstore = [&]() {
 #pragma unroll
@@ -507,12 +567,13 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
             dr = dr < R ? dr : R - 1;
             src[i] = D + (uint64_t)dr * pitch + seg_off[i];
         } else {
-            src[i] = reinterpret_cast<const uint8_t*>(QL) + (uint64_t)(n0 + r) * Cp + seg_off[i];
+            src[i] = reinterpret_cast<const uint8_t*>(QL) + ql_row(n0 + r, Cp) + seg_off[i];
         }
     }
 
     auto issue = [&](uint32_t u) {
         const uint32_t k0 = (kt0 + u) * T::BK;
+        const uint32_t kq = ql_col(k0);     // BK divides 128: a row's k-tile stays in one QL tile
         uint8_t* stage = smem + (u % T::STAGES) * T::STAGE_BYTES;
 #pragma unroll
         for (int i = 0; i < T::LOADS; ++i) {
@@ -522,8 +583,8 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
             // keep old bytes, which meet zero query bytes); QL rows are
             // zero-padded to Cp and always loaded.
             if (!is_a[i] || k0 + seg_off[i] + 16 <= C)
-                __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + k0), (lds_void_t*)dst,
-                                                 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + (is_a[i] ? k0 : kq)),
+                                                 (lds_void_t*)dst, 16, 0, 0);
         }
     };
 
@@ -654,7 +715,7 @@ __global__ __launch_bounds__(256) void k_gemm_roles(const uint8_t* __restrict__ 
             src[i] = D + (uint64_t)dr * pitch + seg_off[i];
         } else {
             src[i] = reinterpret_cast<const uint8_t*>(QL) +
-                     (uint64_t)(n0 + (uint32_t)min(r, T::BN - 1)) * Cp + seg_off[i];
+                     ql_row(n0 + (uint32_t)min(r, T::BN - 1), Cp) + seg_off[i];
         }
     }
     const uint32_t ktiles = (C + T::BK - 1) / T::BK;
@@ -674,10 +735,11 @@ __global__ __launch_bounds__(256) void k_gemm_roles(const uint8_t* __restrict__ 
             }
         } else {
             uint8_t* stage = ringB + (t % T::SB) * T::B_BYTES;
+            const uint32_t kq = ql_col(k0);
 #pragma unroll
             for (int i = 0; i < T::B_LOADS; ++i) {
                 uint8_t* dst = stage + (lw + 2 * i) * 1024;
-                __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + k0), (lds_void_t*)dst,
+                __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + kq), (lds_void_t*)dst,
                                                  16, 0, 0);
             }
         }
@@ -1052,11 +1114,18 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
     k_zero_words<<<(2 * L.Bp + 255) / 256, 256, 0, s>>>(reinterpret_cast<uint32_t*>(colsum),
                                                          2 * L.Bp);
     PIR_LAUNCH_CHECK();
-    dim3 ig(L.Cp / 64, L.Bp / 32);
-    if (io.q_ldj == 1)
-        k_ingest<true><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Cp, QL, colsum);
-    else
-        k_ingest<false><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Cp, QL, colsum);
+    dim3 ig((L.Bp + kIngB - 1) / kIngB, L.Cp / kIngJ);
+    const bool qmajor = io.q_ldj == 1;
+    const bool vec = ((uintptr_t)io.Q % 16 == 0) &&
+                     (qmajor ? (io.q_ldb % 4 == 0 && C % 4 == 0) : (io.q_ldj % 4 == 0 && B % 4 == 0));
+#define PIR_INGEST(QM, V)                                                                  \
+    k_ingest<QM, V><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Bp, L.Cp, QL, colsum)
+    if (qmajor) {
+        if (vec) PIR_INGEST(true, true); else PIR_INGEST(true, false);
+    } else {
+        if (vec) PIR_INGEST(false, true); else PIR_INGEST(false, false);
+    }
+#undef PIR_INGEST
     PIR_LAUNCH_CHECK();
 
     const uint32_t M = rows ? m : (uint32_t)db->rows;
