@@ -403,8 +403,8 @@ def profile_mode(args, dev, stream) -> int:
         a = torch.empty(R, dtype=torch.int32, device=dev)
         ws = db.workspace(0)
         fn = lambda: db.answer(q, out=a, ws=ws)
-    elif args.profile == "batch":
-        B = 64
+    elif args.profile.startswith("batch"):
+        B = int(args.profile[5:] or 64)
         Q = workload.device_u32((C, B), workload.SEED_BASE + 3, dev)
         out = torch.empty((R, B), dtype=torch.int32, device=dev)
         ws = db.workspace(B)

@@ -24,6 +24,8 @@
 // * Shapes with too few row blocks to fill the chip split the columns; the
 //   per-split partial sums go to the workspace and a second kernel adds
 //   them (integer addition modulo 2^32 is exact in any order).
+#include <type_traits>
+
 #include "qpir_internal.h"
 
 namespace {
@@ -249,7 +251,215 @@ const GemvVariant kGemv[] = {
 };
 constexpr uint32_t kNumGemv = sizeof(kGemv) / sizeof(kGemv[0]);
 
+// ---------------------------------------------------------------- few queries
+// Batches of at most 4 queries (and the field form's single query): the same
+// stream over D as k_answer1, with the limb planes of NQ queries staged in
+// LDS and NQ accumulators per row, so D is read once for the whole batch.
+// On the matrix cores a batch is padded to 32 queries (128 limb rows), so
+// for NQ <= 4 this stream is the faster route: per 16 database bytes and
+// query it costs 16 dot4 plus a combine, 1.2 VALU lane-ops per byte and
+// query against the ~4.9 the CUs can spend at full HBM rate.
+//
+// EXACT (field form): each chunk's combined limb products are below 2^45
+// (four dot4 chains of at most 16 * 255 * 255 < 2^21, shifted by 8k) and are
+// added into 64-bit accumulators; D q < 2^63 for C <= 2^23, so the sum is
+// the exact integer, reduced mod p once at the end.
+constexpr int kFewSlice = 2048;   // query words per LDS stage
+
+template <int NQ, int RW, bool VEC, bool EXACT>
+__global__ __launch_bounds__(kThreads) void k_answer_few(
+    const uint8_t* __restrict__ D, uint64_t pitch, uint32_t R, uint32_t C,
+    const uint32_t* __restrict__ Q, uint64_t ldj, uint64_t ldb, uint32_t B,
+    uint32_t cols_per_split, void* __restrict__ part) {
+    typedef typename std::conditional<EXACT, uint64_t, uint32_t>::type acc_t;
+    __shared__ u32x4 s_limb[NQ][4][kFewSlice / 16];
+    __shared__ acc_t s_red[kWaves][RW][65];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t row0 = (blockIdx.x * kWaves + wave) * RW;
+    const uint32_t cb = blockIdx.y * cols_per_split;
+    const uint32_t ce = min(C, cb + cols_per_split);
+
+    const uint8_t* rp[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const uint32_t r = min(row0 + (uint32_t)i, R - 1);
+        rp[i] = D + (uint64_t)r * pitch;
+    }
+    acc_t acc[RW][NQ];
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) acc[i][b] = 0;
+
+    for (uint32_t s0 = cb; s0 < ce; s0 += kFewSlice) {
+        const uint32_t se = min(ce, s0 + (uint32_t)kFewSlice);
+        __syncthreads();   // previous slice fully consumed
+        for (int t = tid; t < NQ * (kFewSlice / 16); t += kThreads) {
+            const int b = t / (kFewSlice / 16);
+            const int g = t % (kFewSlice / 16);
+            const uint32_t c = s0 + 16u * g;
+            uint32_t x[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                x[e] = ((uint32_t)b < B && c + e < se) ? Q[(uint64_t)(c + e) * ldj + (uint64_t)b * ldb]
+                                                       : 0u;
+            uint32_t l[4][4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                uint32_t o[4];
+                limbs_of4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3], o);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) l[k][w] = o[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_limb[b][k][g] = u32x4{l[k][0], l[k][1], l[k][2], l[k][3]};
+        }
+        __syncthreads();
+
+        for (uint32_t c0 = s0; c0 < se; c0 += kChunk) {
+            const uint32_t li = (c0 - s0) / 16 + lane;
+            const uint32_t c = c0 + 16u * lane;
+            u32x4 d[RW];
+            if (VEC && c0 + kChunk <= se) {
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+                    d[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rp[i] + c));
+            } else {
+#pragma unroll
+                for (int i = 0; i < RW; ++i) d[i] = c < se ? load16<VEC>(rp[i], c, se) : u32x4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int b = 0; b < NQ; ++b) {
+                u32x4 L[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) L[k] = s_limb[b][k][li < kFewSlice / 16 ? li : 0];
+#pragma unroll
+                for (int i = 0; i < RW; ++i) {
+                    if (EXACT) {
+                        uint32_t p[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            uint32_t a = __builtin_amdgcn_udot4(d[i].x, L[k].x, 0u, false);
+                            a = __builtin_amdgcn_udot4(d[i].y, L[k].y, a, false);
+                            a = __builtin_amdgcn_udot4(d[i].z, L[k].z, a, false);
+                            p[k] = __builtin_amdgcn_udot4(d[i].w, L[k].w, a, false);
+                        }
+                        acc[i][b] += (uint64_t)p[0] + ((uint64_t)p[1] << 8) +
+                                     ((uint64_t)p[2] << 16) + ((uint64_t)p[3] << 24);
+                    } else {
+                        acc[i][b] += dot16(d[i], L);
+                    }
+                }
+            }
+        }
+    }
+
+    // Sum the 64 lanes of each (row, query); one query at a time through LDS.
+    constexpr int kLanesPerRow = 64 / RW;
+    const int i = lane / kLanesPerRow;
+    const int prt = lane % kLanesPerRow;
+    const uint32_t r = row0 + (uint32_t)i;
+#pragma unroll
+    for (int b = 0; b < NQ; ++b) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < RW; ++t) s_red[wave][t][lane] = acc[t][b];
+        __syncthreads();
+        acc_t v = 0;
+#pragma unroll
+        for (int t = 0; t < RW; ++t) v += s_red[wave][i][prt * RW + t];
+#pragma unroll
+        for (int off = 1; off < kLanesPerRow; off <<= 1) v += __shfl_xor(v, off);
+        if (prt == 0 && r < R && (uint32_t)b < B)
+            static_cast<acc_t*>(part)[((uint64_t)blockIdx.y * B + b) * R + r] = v;
+    }
+}
+
+// Sum of the column splits; the field form reduces mod p.  Output element
+// (r, b) goes to out[r * o_ldr + b * o_ldb].
+template <bool EXACT>
+__global__ void k_few_finish(const void* __restrict__ part, uint32_t R, uint32_t B, uint32_t S,
+                             uint32_t p, uint32_t* __restrict__ out, uint64_t o_ldr,
+                             uint64_t o_ldb) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)R * B) return;
+    const uint32_t b = (uint32_t)(idx / R), r = (uint32_t)(idx % R);
+    uint32_t* dst = out + (uint64_t)r * o_ldr + (uint64_t)b * o_ldb;
+    if (EXACT) {
+        uint64_t v = 0;
+        for (uint32_t s = 0; s < S; ++s)
+            v += static_cast<const uint64_t*>(part)[((uint64_t)s * B + b) * R + r];
+        *dst = (uint32_t)(v % p);
+    } else {
+        uint32_t v = 0;
+        for (uint32_t s = 0; s < S; ++s)
+            v += static_cast<const uint32_t*>(part)[((uint64_t)s * B + b) * R + r];
+        *dst = v;
+    }
+}
+
+template <int NQ>
+constexpr int few_rw() { return NQ == 4 ? 8 : 16; }
+
+uint32_t few_nq(uint32_t B) { return B <= 1 ? 1u : (B <= 2 ? 2u : 4u); }
+
+// Column splits for the few-query stream (as for k_answer1), and the
+// partial buffer: splits x B x R accumulators (8 bytes, enough for both
+// forms).
+SplitPlan few_plan(const pir_db_t* db, uint32_t B) {
+    const uint32_t rw = few_nq(B) == 4 ? 8u : 16u;
+    return plan_splits(db, rw * kWaves);
+}
+
+template <int NQ, bool EXACT>
+pir_status launch_few_t(const pir_db_t* db, const BatchIO& io, uint32_t B, uint32_t modulus,
+                        void* ws, hipStream_t s) {
+    constexpr int RW = few_rw<NQ>();
+    constexpr uint32_t kRows = RW * kWaves;
+    const SplitPlan pl = plan_splits(db, kRows);
+    const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
+    dim3 grid((R + kRows - 1) / kRows, pl.splits);
+    if (db->aligned)
+        k_answer_few<NQ, RW, true, EXACT><<<grid, kThreads, 0, s>>>(
+            db->D, db->pitch, R, C, io.Q, io.q_ldj, io.q_ldb, B, pl.cols_per_split, ws);
+    else
+        k_answer_few<NQ, RW, false, EXACT><<<grid, kThreads, 0, s>>>(
+            db->D, db->pitch, R, C, io.Q, io.q_ldj, io.q_ldb, B, pl.cols_per_split, ws);
+    PIR_LAUNCH_CHECK();
+    const uint64_t n = (uint64_t)R * B;
+    k_few_finish<EXACT><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(
+        ws, R, B, pl.splits, modulus, io.out, io.o_ldr, io.o_ldb);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
 }  // namespace
+
+size_t few_workspace_bytes(const pir_db_t* db, uint32_t B) {
+    if (B == 0 || B > kFewMax) return 0;
+    const SplitPlan pl = few_plan(db, B);
+    return round_up((size_t)pl.splits * B * db->rows * 8, kWsAlign);
+}
+
+pir_status few_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B, uint32_t modulus,
+                            void* ws, size_t ws_bytes, hipStream_t s) {
+    if (B == 0) return PIR_OK;
+    if (B > kFewMax) return PIR_ERR_SHAPE;
+    if (!ws || ws_bytes < few_workspace_bytes(db, B) || ((uintptr_t)ws % kWsAlign))
+        return PIR_ERR_WORKSPACE;
+    const bool exact = modulus != 0;
+    switch (few_nq(B)) {
+        case 1: return exact ? launch_few_t<1, true>(db, io, B, modulus, ws, s)
+                             : launch_few_t<1, false>(db, io, B, modulus, ws, s);
+        case 2: return exact ? launch_few_t<2, true>(db, io, B, modulus, ws, s)
+                             : launch_few_t<2, false>(db, io, B, modulus, ws, s);
+        default: return exact ? launch_few_t<4, true>(db, io, B, modulus, ws, s)
+                              : launch_few_t<4, false>(db, io, B, modulus, ws, s);
+    }
+}
 
 uint32_t gemv_variant_count() { return kNumGemv; }
 

@@ -924,7 +924,7 @@ using Roles128x256A10B4 = Roles<2, 2, 2, 4, 10, 4>;     // 80 + 64 KiB
 using Reg128x256 = Tile<2, 2, 2, 4, 128>;
 using Reg128x128 = Tile<4, 1, 1, 4, 128>;
 
-enum Kind : uint8_t { kAuto, kRing, kRoles, kReg };
+enum Kind : uint8_t { kAuto, kRing, kRoles, kReg, kFew };
 
 struct VariantInfo {
     const char* name;
@@ -946,10 +946,11 @@ const VariantInfo kVariants[] = {
     {"roles_128x256_a10b4", kRoles, 128, 256, 64, launch_roles<Roles128x256A10B4>},
     {"reg_128x256", kReg, 128, 256, 128, launch_reg<Reg128x256>},
     {"reg_128x128", kReg, 128, 128, 128, launch_reg<Reg128x128>},
+    {"few", kFew, 0, 0, 0, nullptr},   // dot4 stream, batches of at most kFewMax
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
-                   kVarReg128 = 11;
+                   kVarReg128 = 11, kVarFew = 12;
 
 bool ring_ok(const pir_db_t* db) { return db->aligned && (db->cols % 16 == 0); }
 
@@ -959,15 +960,26 @@ bool variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
     if (v == 0) return true;
     if (v >= kNumVariants) return false;
     const VariantInfo& vi = kVariants[v];
+    if (vi.kind == kFew) return B <= kFewMax;
     if (vi.kind != kReg && !ring_ok(db)) return false;
     return (4u * padded_batch(B)) % vi.bn == 0;
 }
 
-uint32_t default_variant(const pir_db_t* db, uint32_t B) {
+// Matrix-core choice (any batch size, gathered rows allowed).
+uint32_t default_gemm(const pir_db_t* db, uint32_t B) {
     const uint32_t Bp = padded_batch(B);
     if (!ring_ok(db)) return Bp == 32u ? kVarReg128 : kVarReg256;
     if (Bp == 32u) return kVarRing128;
     return Bp >= 256u ? kVarRingWide : kVarRing256;
+}
+
+// The dot4 stream beats the padded matrix-core tile up to two queries; at
+// four it is bound by VALU issue (measured at 32768 x 32768: 173 vs 254 us
+// for one query, 194 vs 236 us for two, 400 vs 224 us for four).
+constexpr uint32_t kFewDefault = 2;
+
+uint32_t default_variant(const pir_db_t* db, uint32_t B) {
+    return B <= kFewDefault ? kVarFew : default_gemm(db, B);
 }
 
 struct SplitPlan {
@@ -1095,7 +1107,7 @@ bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
 
 size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B) {
     if (B == 0) return 0;
-    return batch_layout(db, B).total;
+    return std::max(batch_layout(db, B).total, few_workspace_bytes(db, B));
 }
 
 pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
@@ -1103,8 +1115,22 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
                              size_t ws_bytes, hipStream_t s) {
     const uint32_t C = (uint32_t)db->cols;
     const bool exact = modulus != 0;
-    if (exact && (!ring_ok(db) || rows)) return PIR_ERR_UNSUPPORTED;
+    if (exact && rows) return PIR_ERR_UNSUPPORTED;
     if (exact && C > kMaxExactCols) return PIR_ERR_SHAPE;
+    // The reported size is the contract for every kernel path.
+    if (!ws || ws_bytes < mfma_workspace_bytes(db, B) || ((uintptr_t)ws % kWsAlign))
+        return PIR_ERR_WORKSPACE;
+
+    uint32_t v = db->variant[batch_bucket(B)];
+    if (v == 0 || !variant_valid(db, B, v)) v = default_variant(db, B);
+    if (rows && kVariants[v].kind == kFew) v = default_gemm(db, B);
+    if (exact && kVariants[v].kind != kRing && kVariants[v].kind != kFew)
+        v = (B <= kFewDefault || (B <= kFewMax && !ring_ok(db))) ? kVarFew : default_gemm(db, B);
+    if (exact && (kVariants[v].kind == kReg || kVariants[v].kind == kRoles ||
+                  (kVariants[v].kind == kRing && !ring_ok(db))))
+        return PIR_ERR_UNSUPPORTED;   // field form beyond kFewMax queries needs the ring kernels
+    if (kVariants[v].kind == kFew) return few_answer_batch(db, io, B, modulus, ws, ws_bytes, s);
+
     const BatchLayout L = batch_layout(db, B);
     if (!ws || ws_bytes < L.total || ((uintptr_t)ws % kWsAlign)) return PIR_ERR_WORKSPACE;
     uint8_t* base = static_cast<uint8_t*>(ws);
@@ -1130,9 +1156,6 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
 
     const uint32_t M = rows ? m : (uint32_t)db->rows;
     if (M == 0) return PIR_OK;
-    uint32_t v = db->variant[batch_bucket(B)];
-    if (v == 0 || !variant_valid(db, B, v)) v = default_variant(db, B);
-    if (exact && kVariants[v].kind != kRing) v = default_variant(db, B);
     const VariantInfo& vi = kVariants[v];
     const SplitPlan sp = plan_splits(M, L.N, C, vi, exact);
     if (sp.splits > 1 && L.part_off + (size_t)sp.splits * M * B * 8 > L.total)

@@ -67,6 +67,13 @@ size_t gemv_workspace_bytes(const pir_db_t* db);
 pir_status gemv_answer(const pir_db_t* db, const uint32_t* q, uint32_t* a, void* ws,
                        size_t ws_bytes, hipStream_t s);
 
+// Batches of at most kFewMax queries streamed with dot4 instead of the
+// matrix cores (answer_gemv.hip); modulus 0 = mod 2^32, else the field form.
+constexpr uint32_t kFewMax = 4;
+size_t few_workspace_bytes(const pir_db_t* db, uint32_t B);
+pir_status few_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B, uint32_t modulus,
+                            void* ws, size_t ws_bytes, hipStream_t s);
+
 // ---- database metadata (db.hip)
 pir_status launch_rowsum(const pir_db_t* db, const uint32_t* rows, uint32_t m, hipStream_t s);
 pir_status launch_scatter_rows(const pir_db_t* db, const uint32_t* rows, uint32_t m,

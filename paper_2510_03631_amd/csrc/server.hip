@@ -142,8 +142,10 @@ struct pir_server {
             hipHostMalloc((void**)&s.h_O, (size_t)mb * d.R * 4, hipHostMallocDefault) != hipSuccess)
             return PIR_ERR_NO_MEMORY;
         memset(s.h_Q, 0, (size_t)mb * d.C * 4);
-        s.ws_bytes = std::max(pir_workspace_bytes(d.db, 0),
-                              mb > 1 ? pir_workspace_bytes(d.db, mb) : (size_t)0);
+        // Every power-of-two size the slot launches (small batches take a
+        // different kernel path with its own workspace need).
+        s.ws_bytes = pir_workspace_bytes(d.db, 0);
+        for (uint32_t b = 2; b <= mb; b *= 2) s.ws_bytes = std::max(s.ws_bytes, pir_workspace_bytes(d.db, b));
         if (hipMalloc((void**)&s.d_Q, (size_t)mb * d.C * 4) != hipSuccess ||
             hipMalloc((void**)&s.d_O, (size_t)mb * d.R * 4) != hipSuccess ||
             (s.ws_bytes && hipMalloc(&s.d_ws, s.ws_bytes) != hipSuccess))

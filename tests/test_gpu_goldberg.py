@@ -189,11 +189,12 @@ def test_modp_error_paths(qp):
         assert lib().pir_answer_batch_modp(db.handle, Q.data_ptr(), 4, P, out.data_ptr(),
                                            None, 0, None) == 6
         torch.cuda.synchronize()
-    # Unaligned rows: the field form needs the ring kernels.
+    # Unaligned rows: beyond 4 queries the field form needs the ring kernels.
     store = torch.zeros(64 * 128 + 1, dtype=torch.uint8, device="cuda")
+    Q5 = torch.zeros((128, 5), dtype=torch.int32, device="cuda")
     with qp.Database(store[1:].view(64, 128)) as db:
         with pytest.raises(qp.PirError) as ei:
-            db.answer_batch_modp(Q, P)
+            db.answer_batch_modp(Q5, P)
         assert ei.value.status == UNSUPPORTED
     # More than 2^23 columns (checked before the workspace).
     wide = torch.zeros((1, (1 << 23) + 16), dtype=torch.uint8, device="cuda")
