@@ -395,6 +395,24 @@ def profile_mode(args, dev, stream) -> int:
         return 0
     if args.profile.startswith(("chor", "oop", "ftr")):
         return profile_instantiation(args, dev, stream)
+    if args.profile == "intmm":
+        # Reference point, not a product path: the vendor library's plain
+        # int8 GEMM (torch._int_mm, hipBLASLt) at the hint and 64-query
+        # shapes (M = R, K = C, N = 4 limbs x queries), int32 out.
+        for N in (4 * n, 4 * 64):
+            a = torch.randint(-128, 127, (R, C), dtype=torch.int8, device=dev)
+            b = torch.randint(-128, 127, (N, C), dtype=torch.int8, device=dev).t()
+            fn = lambda: torch._int_mm(a, b)
+            for _ in range(args.warmup):
+                fn()
+            wall, ev = time_on_stream(fn, args.steps, stream)
+            t = ev / args.steps
+            print(json.dumps({"profile": "intmm", "M": R, "K": C, "N": N,
+                              "avg_us": round(t * 1e6, 2),
+                              "tops": round(2.0 * R * C * N / t / 1e12, 1)}))
+            del a, b
+            torch.cuda.empty_cache()
+        return 0
     D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
     db = qp.Database(D)
     tune.apply(db)
