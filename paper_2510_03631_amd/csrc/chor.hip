@@ -17,9 +17,10 @@
 //   loaded 8 at a time, back to back;
 // * batches of at most 4 queries (k_chor_stream) read only the rows that
 //   some query selects (a single query touches half of the database): the
-//   selector words of a whole slab are fetched up front, set bits are taken
-//   with a wave-uniform bit scan, and up to 16 rows per wave are in flight
-//   (non-temporal loads); each row is XORed into every query under a mask;
+//   selector words of a whole slab are fetched up front, set bits of 64-row
+//   pairs of blocks are taken with a wave-uniform bit scan, and up to 32
+//   rows per wave are in flight (non-temporal loads); each row is XORed into
+//   every query under a mask;
 // * larger batches (k_chor) build, per 4 rows, the 16 XOR combinations of
 //   the rows in a wave-private LDS table and add one table entry per query
 //   (method of the Four Russians): one LDS read and XOR per query per 4 rows;
@@ -63,12 +64,13 @@ __device__ inline uint32_t xcd_remap(uint32_t bid, uint32_t nblk) {
     return bid < per * 8u ? (bid % 8u) * per + bid / 8u : bid;
 }
 
-// Batches of at most G queries (G * 16 <= 64).  Workgroup = one slab of rows
+// Batches of at most G queries (G <= 4).  Workgroup = one slab of rows
 // [r0, r1), all columns in chunks of 1024 words (lane t: words 4t..4t+3).
 // One load per lane fetches the selector words of 64 / G consecutive 32-row
-// blocks (lane l: query l / (64/G), block l % (64/G)); per block the OR of the
-// queries' words names the rows to read, taken kDepth at a time.
-constexpr int kDepth = 16;
+// blocks (lane l: query l / (64/G), block l % (64/G)).  Blocks are taken in
+// pairs: the OR of the queries' 64-bit masks names the rows to read, up to
+// kDepth of them in flight per wave.
+constexpr int kDepth = 32;
 
 template <int G, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_chor_stream(const uint32_t* __restrict__ DB,
@@ -79,6 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_chor_stream(const uint32_t* __rest
                                                           uint32_t slab_rows,
                                                           uint32_t* __restrict__ out) {
     constexpr uint32_t kBlocks = 64 / G;
+    static_assert(kBlocks % 2 == 0, "blocks are taken in pairs");
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t slab = xcd_remap(blockIdx.x, gridDim.x);
@@ -104,14 +107,16 @@ __global__ __launch_bounds__(kThreads) void k_chor_stream(const uint32_t* __rest
                     if (nrow < 32u) qv &= (1u << nrow) - 1u;
                 }
             }
-            for (uint32_t jb = 0; jb < kBlocks; ++jb) {
+            for (uint32_t jb = 0; jb < kBlocks; jb += 2) {
                 const uint32_t rblk = base + 32u * jb;
                 if (rblk >= r1) break;                    // uniform
-                uint32_t sel[G];
-                uint32_t any = 0;
+                uint64_t sel[G];
+                uint64_t any = 0;
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    sel[g] = __builtin_amdgcn_readlane(qv, g * (int)kBlocks + (int)jb);
+                    const uint32_t lo = __builtin_amdgcn_readlane(qv, g * (int)kBlocks + (int)jb);
+                    const uint32_t hi = __builtin_amdgcn_readlane(qv, g * (int)kBlocks + (int)jb + 1);
+                    sel[g] = (uint64_t)lo | ((uint64_t)hi << 32);
                     any |= sel[g];
                 }
                 while (any) {
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_chor_stream(const uint32_t* __rest
                         idx[k] = 0;
                         d[k] = u32x4{0, 0, 0, 0};
                         if (any) {                        // uniform
-                            idx[k] = (uint32_t)__builtin_ctz(any);
+                            idx[k] = (uint32_t)__builtin_ctzll(any);
                             any &= any - 1u;
                             if (active)
                                 d[k] = load_words_nt<VEC>(DB + (uint64_t)(rblk + idx[k]) * pitch,
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_chor_stream(const uint32_t* __rest
                     for (int g = 0; g < G; ++g) {
 #pragma unroll
                         for (int k = 0; k < kDepth; ++k) {
-                            const uint32_t m = 0u - ((sel[g] >> idx[k]) & 1u);
+                            const uint32_t m = 0u - (uint32_t)((sel[g] >> idx[k]) & 1u);
                             acc[g] ^= d[k] & u32x4{m, m, m, m};
                         }
                     }
@@ -309,15 +314,20 @@ pir_status launch_chor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint
     return PIR_OK;
 }
 
+template <int G>
 pir_status launch_stream(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
                          const uint32_t* d_Q, uint32_t B, uint32_t* d_out, hipStream_t s) {
-    constexpr int G = 4;
     const uint32_t qwords = (rows + 31) / 32;
-    // About two workgroups per CU: enough rows in flight to stream HBM, few
-    // enough slabs to keep the output atomics (slabs x B x words) down.
-    uint64_t slab = (rows + 511u) / 512u;
+    // Enough rows in flight to stream HBM (32 per wave), few enough slabs to
+    // keep the output atomics (slabs x B x words, all onto the same B rows
+    // of words) down: at most one workgroup per CU for a single query, two
+    // for more, and at least 256 rows per slab.  (Measured on 2^18 and 2^16
+    // rows of 3 KB: fewer workgroups starve the stream on the large
+    // database, more slabs spend the small one's time in atomics.)
+    const uint32_t target = G == 1 ? 256u : 512u;
+    uint64_t slab = (rows + target - 1) / target;
     slab = (slab + 31) / 32 * 32;
-    if (slab < 32) slab = 32;
+    if (slab < 256) slab = 256;
     const uint64_t blocks = (rows + slab - 1) / slab;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
     const bool vec = ((uintptr_t)d_DB % 16 == 0) && (words % 4 == 0) && (pitch % 4 == 0);
@@ -359,7 +369,8 @@ pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_
     // Small batches stream every row under masks; larger ones use the
     // 4-row tables.  Fewer, longer slabs for large batches keep the number of
     // output atomics down.
-    if (B <= 4) return launch_stream(d_DB, rows, words, pitch, d_Q, B, d_out, s);
+    if (B == 1) return launch_stream<1>(d_DB, rows, words, pitch, d_Q, B, d_out, s);
+    if (B <= 4) return launch_stream<4>(d_DB, rows, words, pitch, d_Q, B, d_out, s);
     if (B <= 64) return launch_chor<16, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
     return launch_chor<32, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
 }
