@@ -9,21 +9,24 @@
 //
 // Boolean XOR has no matrix-core form (the paper makes the same point for
 // tensor cores), so this is a VALU / HBM kernel.  Design for gfx950:
-// * a workgroup (256 threads) owns a slab of rows, a group of up to G = 16
-//   queries and a 1024-word column chunk: lane t holds words 4t..4t+3 of the
-//   chunk for every query of the group (G x 16-byte accumulators);
-// * per 32-row block the group's selector words are loaded once (lane g
-//   holds query g's word; wave-uniform reads pick bits out), and rows are
-//   loaded 8 at a time, back to back;
+// * a workgroup (256 threads) owns a slab of rows and a range of columns; a
+//   lane holds 4 consecutive words (16 bytes) of the block for each query it
+//   serves, so every row load is a coalesced 16-byte-per-lane read and the
+//   accumulators are G x 16 bytes per lane;
+// * selector words are loaded once per 32-row block and read with
+//   wave-uniform lane reads, so row choices never diverge within a wave;
 // * batches of at most 4 queries (k_chor_stream) read only the rows that
 //   some query selects (a single query touches half of the database): the
 //   selector words of a whole slab are fetched up front, set bits of 64-row
 //   pairs of blocks are taken with a wave-uniform bit scan, and up to 32
 //   rows per wave are in flight (non-temporal loads); each row is XORed into
 //   every query under a mask;
-// * larger batches (k_chor) build, per 4 rows, the 16 XOR combinations of
-//   the rows in a wave-private LDS table and add one table entry per query
-//   (method of the Four Russians): one LDS read and XOR per query per 4 rows;
+// * larger batches (k_chor_shared) build, per 4 rows, the 16 XOR
+//   combinations of the rows in an LDS table and add one table entry per
+//   query (method of the Four Russians): one LDS read and XOR per query per
+//   4 rows.  The four waves of a workgroup cover one column slice with
+//   different query groups and share each table (built once for 4G
+//   queries, double-buffered, one barrier per 4 rows);
 // * workgroups are numbered slab-major and dealt to XCDs in contiguous
 //   ranges, so the query groups of one slab share its rows in L2;
 // * slabs combine into the output with atomicXor (XOR is associative and
@@ -160,156 +163,148 @@ __global__ __launch_bounds__(kThreads) void k_chor_stream(const uint32_t* __rest
     }
 }
 
-// Work of one workgroup: rows [r0, r1) of a slab, queries [b0, b0 + nb) of a
-// group, all columns in chunks of 1024 words (lane t: words 4t..4t+3).
-//
-// TABLE == false (batches of at most 4): every row is streamed and XORed
-// under a wave-uniform mask, acc_g ^= row & -(bit), no branches.
-// TABLE == true: for every 4 consecutive rows the wave writes the 16 XOR
-// combinations of its slice into a private LDS table (method of the Four
-// Russians); each query then costs one LDS read at the index given by its
-// 4 selector bits and one XOR, instead of a test and XOR per row.
-template <int G, bool TABLE, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_chor(const uint32_t* __restrict__ DB, uint64_t pitch,
-                                                   uint32_t rows, uint32_t W,
-                                                   const uint32_t* __restrict__ Q, uint32_t qwords,
-                                                   uint32_t B, uint32_t slab_rows,
-                                                   uint32_t n_groups, uint32_t* __restrict__ out) {
-    extern __shared__ __attribute__((aligned(16))) u32x4 s_table[];   // [wave][16][64]
+// Larger batches, shared tables.  The four waves of a workgroup cover the
+// same 256-word column slice (lane t: words 4t..4t+3) with different groups
+// of G queries (4G per workgroup), so each 4-row XOR table is built once for
+// all of them: entry e = (hi part: rows 2-3 by e >> 2) xor (lo part: rows
+// 0-1 by e & 3); wave w writes entries 4w .. 4w+3 (entry 0 is kept zero).
+// Tables are double-buffered in LDS; one barrier per 4-row step (LDS
+// counter only, so row loads issued two steps ahead stay in flight) makes a
+// step's table visible and, being passed only after every wave finished the
+// previous step's lookups, frees the other buffer for the next build.
+__device__ inline void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((0x3F & 0xF) | ((0x3F >> 4) << 14) | (0x7 << 4) | (0x0 << 8));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int G, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_chor_shared(const uint32_t* __restrict__ DB,
+                                                          uint64_t pitch, uint32_t rows,
+                                                          uint32_t W,
+                                                          const uint32_t* __restrict__ Q,
+                                                          uint32_t qwords, uint32_t B,
+                                                          uint32_t slab_rows, uint32_t n_qg,
+                                                          uint32_t n_cs,
+                                                          uint32_t* __restrict__ out) {
+    __shared__ u32x4 s_tab[2][16][64];            // [buffer][entry][lane], 32 KiB
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    u32x4* tab = s_table + wave * 16 * 64;
-
-    uint32_t bid = blockIdx.x;
-    {
-        const uint32_t per = gridDim.x / 8u;
-        if (bid < per * 8u) bid = (bid % 8u) * per + bid / 8u;
-    }
-    const uint32_t slab = bid / n_groups;
-    const uint32_t grp = bid % n_groups;
+    // Workgroups of one slab and column slice are consecutive (their query
+    // groups read the same rows), slabs outermost.
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t qg = bid % n_qg;
+    const uint32_t cs = (bid / n_qg) % n_cs;
+    const uint32_t slab = bid / (n_qg * n_cs);
     const uint32_t r0 = slab * slab_rows;
     const uint32_t r1 = min(rows, r0 + slab_rows);
-    const uint32_t b0 = grp * G;
-    const uint32_t nb = min((uint32_t)G, B - b0);
-    if (TABLE) tab[lane] = u32x4{0, 0, 0, 0};   // entry 0: no row selected
+    const uint32_t w = cs * 256u + 4u * lane;
+    const bool active = w < W;
+    const uint32_t qbase = (qg * 4u + (uint32_t)wave) * G;
+    const uint32_t nq = qbase < B ? min((uint32_t)G, B - qbase) : 0u;
 
-    for (uint32_t c0 = 0; c0 < W; c0 += kChunkWords) {
-        // A wave whose 64 lanes all lie past the last word has nothing to do
-        // in this chunk (3 KB blocks leave the fourth wave idle); the waves
-        // never synchronize with each other, so it moves on.
-        if (c0 + 256u * (uint32_t)wave >= W) continue;
-        const uint32_t w = c0 + 4u * threadIdx.x;
-        const bool active = w < W;
-        u32x4 acc[G];
+    if (wave < 2) s_tab[wave][0][lane] = u32x4{0, 0, 0, 0};
+    u32x4 acc[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = u32x4{0, 0, 0, 0};
+    for (int g = 0; g < G; ++g) acc[g] = u32x4{0, 0, 0, 0};
 
-        for (uint32_t r = r0; r < r1; r += 32) {
-            const uint32_t nrow = min(32u, r1 - r);
-            const uint32_t valid = nrow == 32 ? 0xFFFFFFFFu : ((1u << nrow) - 1u);
-            // Lane g < nb holds query g's 32 selector bits for this block.
-            const uint32_t qv = (uint32_t)lane < nb ? (Q[(uint64_t)(b0 + lane) * qwords + r / 32] & valid)
-                                                    : 0u;
-#pragma unroll 1
-            for (int s8 = 0; s8 < 32; s8 += 8) {
-                u32x4 d[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    d[k] = u32x4{0, 0, 0, 0};
-                    if ((uint32_t)(s8 + k) < nrow && active)
-                        d[k] = load_words<VEC>(DB + (uint64_t)(r + s8 + k) * pitch, w, W);
-                }
-                if (!TABLE) {
-#pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        const uint32_t q = __builtin_amdgcn_readlane(qv, g);
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) {
-                            const uint32_t m = 0u - ((q >> (s8 + k)) & 1u);
-                            acc[g] ^= d[k] & u32x4{m, m, m, m};
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const u32x4 x0 = d[4 * h], x1 = d[4 * h + 1], x2 = d[4 * h + 2],
-                                    x3 = d[4 * h + 3];
-                        const u32x4 t3 = x0 ^ x1, t5 = x2 ^ x0, t6 = x2 ^ x1, t7 = x2 ^ t3;
-                        // Entries 1..15 (entry i XORs the rows whose bit is set in i).
-                        tab[1 * 64 + lane] = x0;
-                        tab[2 * 64 + lane] = x1;
-                        tab[3 * 64 + lane] = t3;
-                        tab[4 * 64 + lane] = x2;
-                        tab[5 * 64 + lane] = t5;
-                        tab[6 * 64 + lane] = t6;
-                        tab[7 * 64 + lane] = t7;
-                        tab[8 * 64 + lane] = x3;
-                        tab[9 * 64 + lane] = x3 ^ x0;
-                        tab[10 * 64 + lane] = x3 ^ x1;
-                        tab[11 * 64 + lane] = x3 ^ t3;
-                        tab[12 * 64 + lane] = x3 ^ x2;
-                        tab[13 * 64 + lane] = x3 ^ t5;
-                        tab[14 * 64 + lane] = x3 ^ t6;
-                        tab[15 * 64 + lane] = x3 ^ t7;
-                        // Each lane reads only its own column of the table
-                        // (entry * 64 + lane), so the table is per-lane data:
-                        // program order alone orders these reads after the
-                        // writes above and before the next writes.
-                        // Lookups in batches of 8: the reads are issued together
-                        // so that several are in flight before the XORs wait.
-                        const int sh = s8 + 4 * h;
-#pragma unroll
-                        for (int g0 = 0; g0 < G; g0 += 8) {
-                            u32x4 t[8];
-#pragma unroll
-                            for (int g = 0; g < 8; ++g) {
-                                const uint32_t idx =
-                                    (__builtin_amdgcn_readlane(qv, g0 + g) >> sh) & 15u;
-                                t[g] = tab[idx * 64 + lane];
-                            }
-#pragma unroll
-                            for (int g = 0; g < 8; ++g) acc[g0 + g] ^= t[g];
-                        }
-                    }
-                }
-                if ((uint32_t)(s8 + 8) >= nrow) break;
-            }
+    // Rows this wave needs for its entries: 0 and 1 always; 2 for waves 1
+    // and 3; 3 for waves 2 and 3.
+    const bool need2 = wave == 1 || wave == 3;
+    const bool need3 = wave >= 2;
+    auto load_row = [&](uint32_t r) -> u32x4 {
+        return (active && r < r1) ? load_words_nt<VEC>(DB + (uint64_t)r * pitch, w, W)
+                                  : u32x4{0, 0, 0, 0};
+    };
+    auto load_step = [&](uint32_t st, u32x4 (&x)[4]) {
+        const uint32_t r = r0 + 4u * st;
+        x[0] = load_row(r);
+        x[1] = load_row(r + 1);
+        x[2] = need2 ? load_row(r + 2) : u32x4{0, 0, 0, 0};
+        x[3] = need3 ? load_row(r + 3) : u32x4{0, 0, 0, 0};
+    };
+    auto load_sel = [&](uint32_t blk) -> uint32_t {
+        const uint32_t b = qbase + (uint32_t)lane;
+        return ((uint32_t)lane < nq && 32u * blk < rows) ? Q[(uint64_t)b * qwords + blk] : 0u;
+    };
+
+    const uint32_t nsteps = r1 > r0 ? (r1 - r0 + 3u) / 4u : 0u;
+    u32x4 xa[4], xb[4];
+    load_step(0, xa);
+    load_step(1, xb);
+    uint32_t qv = 0, qv_next = load_sel(r0 / 32u);
+
+    auto step = [&](uint32_t st, u32x4 (&x)[4]) {
+        const int buf = st & 1;
+        if (st % 8u == 0) {
+            qv = qv_next;
+            qv_next = load_sel(r0 / 32u + st / 8u + 1u);
         }
-        if (active) {
+        const u32x4 lo1 = x[0], lo2 = x[1], lo3 = x[0] ^ x[1];
+        const u32x4 hi = wave == 0 ? u32x4{0, 0, 0, 0}
+                                   : (wave == 1 ? x[2] : (wave == 2 ? x[3] : x[2] ^ x[3]));
+        if (wave != 0) s_tab[buf][4 * wave][lane] = hi;
+        s_tab[buf][4 * wave + 1][lane] = hi ^ lo1;
+        s_tab[buf][4 * wave + 2][lane] = hi ^ lo2;
+        s_tab[buf][4 * wave + 3][lane] = hi ^ lo3;
+        if (st + 2u < nsteps) load_step(st + 2u, x);    // prefetch two steps ahead
+        lds_barrier();
+        const int sh = 4 * (int)(st % 8u);
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if ((uint32_t)g < nb) {
-                    uint32_t* o = out + (uint64_t)(b0 + g) * W + w;
-                    if (acc[g].x) atomicXor(o, acc[g].x);
-                    if (w + 1 < W && acc[g].y) atomicXor(o + 1, acc[g].y);
-                    if (w + 2 < W && acc[g].z) atomicXor(o + 2, acc[g].z);
-                    if (w + 3 < W && acc[g].w) atomicXor(o + 3, acc[g].w);
-                }
+        for (int g0 = 0; g0 < G; g0 += 8) {
+            u32x4 t[8];
+#pragma unroll
+            for (int g = 0; g < 8 && g0 + g < G; ++g) {
+                const uint32_t idx = (__builtin_amdgcn_readlane(qv, g0 + g) >> sh) & 15u;
+                t[g] = s_tab[buf][idx][lane];
+            }
+#pragma unroll
+            for (int g = 0; g < 8 && g0 + g < G; ++g) acc[g0 + g] ^= t[g];
+        }
+    };
+    for (uint32_t st = 0; st < nsteps; st += 2) {
+        step(st, xa);
+        if (st + 1 < nsteps) step(st + 1, xb);
+    }
+
+    if (active) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if ((uint32_t)g < nq) {
+                uint32_t* o = out + (uint64_t)(qbase + g) * W + w;
+                if (acc[g].x) atomicXor(o, acc[g].x);
+                if (w + 1 < W && acc[g].y) atomicXor(o + 1, acc[g].y);
+                if (w + 2 < W && acc[g].z) atomicXor(o + 2, acc[g].z);
+                if (w + 3 < W && acc[g].w) atomicXor(o + 3, acc[g].w);
             }
         }
     }
 }
 
-template <int G, bool TABLE>
-pir_status launch_chor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
-                       const uint32_t* d_Q, uint32_t B, uint32_t* d_out, uint32_t target_blocks,
-                       hipStream_t s) {
+template <int G>
+pir_status launch_shared(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
+                         const uint32_t* d_Q, uint32_t B, uint32_t* d_out, uint32_t target,
+                         hipStream_t s) {
     const uint32_t qwords = (rows + 31) / 32;
-    const uint32_t n_groups = (B + G - 1) / G;
-    uint64_t slab = ((uint64_t)rows * n_groups + target_blocks - 1) / target_blocks;
+    const uint32_t n_qg = (B + 4 * G - 1) / (4 * G);
+    const uint32_t n_cs = (words + 255) / 256;
+    const uint64_t per_slab = (uint64_t)n_qg * n_cs;
+    uint64_t n_slabs = target / per_slab;
+    if (n_slabs < 1) n_slabs = 1;
+    uint64_t slab = (rows + n_slabs - 1) / n_slabs;
     slab = (slab + 31) / 32 * 32;
     if (slab < 32) slab = 32;
-    const uint64_t n_slabs = (rows + slab - 1) / slab;
-    const uint64_t blocks = n_slabs * n_groups;
+    n_slabs = (rows + slab - 1) / slab;
+    const uint64_t blocks = n_slabs * per_slab;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
-    const size_t lds = TABLE ? (size_t)4 * 16 * 64 * sizeof(u32x4) : 0;
     const bool vec = ((uintptr_t)d_DB % 16 == 0) && (words % 4 == 0) && (pitch % 4 == 0);
     if (vec)
-        k_chor<G, TABLE, true><<<(uint32_t)blocks, kThreads, lds, s>>>(
-            d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_groups, d_out);
+        k_chor_shared<G, true><<<(uint32_t)blocks, kThreads, 0, s>>>(
+            d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
     else
-        k_chor<G, TABLE, false><<<(uint32_t)blocks, kThreads, lds, s>>>(
-            d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_groups, d_out);
+        k_chor_shared<G, false><<<(uint32_t)blocks, kThreads, 0, s>>>(
+            d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
     PIR_LAUNCH_CHECK();
     return PIR_OK;
 }
@@ -371,8 +366,10 @@ pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_
     // output atomics down.
     if (B == 1) return launch_stream<1>(d_DB, rows, words, pitch, d_Q, B, d_out, s);
     if (B <= 4) return launch_stream<4>(d_DB, rows, words, pitch, d_Q, B, d_out, s);
-    if (B <= 64) return launch_chor<16, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
-    return launch_chor<32, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
+    if (B <= 16) return launch_shared<4>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
+    if (B <= 32) return launch_shared<8>(d_DB, rows, words, pitch, d_Q, B, d_out, 1024, s);
+    if (B <= 256) return launch_shared<16>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
+    return launch_shared<32>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
 }
 
 extern "C" {
