@@ -519,6 +519,17 @@ struct Ring {
     static_assert(NW == 4 || NW == 8, "four or eight waves");
     static_assert(TN % 4 == 0, "a wave covers whole groups of four limbs");
     static_assert(BLOCKS % NW == 0, "blocks split evenly over waves");
+    static_assert(A_BLOCKS % NW == 0, "a wave's first A_LOADS loads carry D rows");
+    static constexpr int A_LOADS = A_BLOCKS / NW;
+    // The loads of the tile that refills a freed slot are spread over all
+    // KS k-steps of a stage when another tile is in flight (three or more
+    // stages), else over the fewest k-steps that fit (one load per MFMA),
+    // so the tile has the rest of the stage to land.
+    static constexpr int KS = BK / 32;
+    static constexpr int FIT = (LOADS + TM * TN - 1) / (TM * TN);
+    static constexpr int ISSUE_STEPS = STAGES > 2 ? KS : (FIT < KS ? FIT : KS);
+    static_assert((LOADS + ISSUE_STEPS - 1) / ISSUE_STEPS <= TM * TN,
+                  "a k-step's share of the loads fits between its MFMAs");
     static_assert((STAGES - 2) * LOADS < 64, "vmcnt range");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
@@ -547,45 +558,43 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     const uint32_t ktiles = kt0 < ktiles_all ? min(kts, ktiles_all - kt0) : 0u;
 
     // Per-lane source of each of this wave's LOADS block loads: lane l of a
-    // load fills slot l % SEGS of row l / SEGS of a 1 KiB block.
+    // load fills slot l % SEGS of row l / SEGS of a 1 KiB block.  Loads
+    // i < A_LOADS carry D rows, the rest QL rows.
     const int lrow = lane / T::SEGS;
     const uint8_t* src[T::LOADS];
     uint32_t seg_off[T::LOADS];
-    bool is_a[T::LOADS];
 #pragma unroll
     for (int i = 0; i < T::LOADS; ++i) {
+        const bool a = i < T::A_LOADS;
         const int kb = wave + T::NW * i;
-        const bool a = kb < T::A_BLOCKS;
         const int r = (a ? kb : kb - T::A_BLOCKS) * T::RPB + lrow;
         const int seg = swz<T::BK>(r, lane % T::SEGS);
-        is_a[i] = a;
         seg_off[i] = 16u * seg;
         if (a) {
             uint32_t mi = m0 + r;
             mi = mi < M ? mi : M - 1;
             uint32_t dr = GATHER ? e.rows[mi] : mi;
             dr = dr < R ? dr : R - 1;
-            src[i] = D + (uint64_t)dr * pitch + seg_off[i];
+            src[i] = D + (uint64_t)dr * pitch;
         } else {
             src[i] = reinterpret_cast<const uint8_t*>(QL) + ql_row(n0 + r, Cp) + seg_off[i];
         }
     }
 
-    auto issue = [&](uint32_t u) {
-        const uint32_t k0 = (kt0 + u) * T::BK;
-        const uint32_t kq = ql_col(k0);     // BK divides 128: a row's k-tile stays in one QL tile
-        uint8_t* stage = smem + (u % T::STAGES) * T::STAGE_BYTES;
-#pragma unroll
-        for (int i = 0; i < T::LOADS; ++i) {
-            const int kb = wave + T::NW * i;
-            uint8_t* dst = stage + kb * 1024;   // A blocks first, then B blocks
-            // D segments past the last column are skipped (their LDS slots
-            // keep old bytes, which meet zero query bytes); QL rows are
-            // zero-padded to Cp and always loaded.
-            if (!is_a[i] || k0 + seg_off[i] + 16 <= C)
-                __builtin_amdgcn_global_load_lds((glb_void_t*)(src[i] + (is_a[i] ? k0 : kq)),
-                                                 (lds_void_t*)dst, 16, 0, 0);
-        }
+    // Load i of k-tile t into its ring slot.  Every load is issued, so each
+    // wave has the same count in flight per tile:
+    // * a D segment past column C reads the row's last 16 bytes instead (C
+    //   is a multiple of 16); those bytes meet zero-padded query bytes;
+    // * t past the piece's last tile is clamped to it: such a load refills a
+    //   slot no later iteration reads.
+    const uint32_t t_last = ktiles ? ktiles - 1 : 0;
+    auto issue_one = [&](uint32_t t, int i) {
+        const uint32_t tt = min(t, t_last);
+        const uint32_t k0 = (kt0 + tt) * T::BK;
+        uint8_t* dst = smem + (t % T::STAGES) * T::STAGE_BYTES + (wave + T::NW * i) * 1024;
+        const uint8_t* p = i < T::A_LOADS ? src[i] + min(k0 + seg_off[i], C - 16u)
+                                          : src[i] + ql_col(k0);   // BK divides 128
+        __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)dst, 16, 0, 0);
     };
 
     i32x16 acc[T::TM][T::TN];
@@ -599,56 +608,91 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     const int frow = lane & 31;
     const int fseg = lane >> 5;
     const u32x4 centre = u32x4{kCentreWord, kCentreWord, kCentreWord, kCentreWord};
+    constexpr int KS = T::KS;
 
-#pragma unroll
-    for (int p = 0; p < T::STAGES - 1; ++p)
-        if ((uint32_t)p < ktiles) issue(p);
-
-    for (uint32_t u = 0; u < ktiles; ++u) {
-        // Tiles u+1 .. u+STAGES-2 were issued after tile u.  While none of
-        // them is the piece's last tile (whose D loads past column C may be
-        // skipped by a whole wave, issuing fewer loads), tile u has landed
-        // once at most (STAGES-2) * LOADS of this wave's loads are
-        // outstanding (loads complete in order).  Otherwise wait for all.
-        // The barrier then makes every wave's part visible and frees the
-        // stage consumed in the previous iteration.
-        if (u + T::STAGES - 1 < ktiles) wait_vmcnt<(T::STAGES - 2) * T::LOADS>();
-        else wait_vmcnt<0>();
-        ring_barrier();
-        if (u + T::STAGES - 1 < ktiles) issue(u + T::STAGES - 1);
-
+    // Fragments of one k-step of tile u (buffer buf).
+    u32x4 fa[2][T::TM];
+    i32x4 fb[2][T::TN];
+    auto read_frags = [&](uint32_t u, int ks, int buf) {
         const uint8_t* sa = smem + (u % T::STAGES) * T::STAGE_BYTES;
         const uint8_t* sb = sa + T::A_BYTES;
-        // Fragments of k-step ks+1 are read while the MFMAs of ks run.
-        constexpr int KS = T::BK / 32;
-        i32x4 fa[2][T::TM], fb[2][T::TN];
-        auto read_frags = [&](int ks, int buf) {
-            const int seg = 2 * ks + fseg;
+        const int seg = 2 * ks + fseg;
 #pragma unroll
-            for (int a = 0; a < T::TM; ++a) {
-                const int r = wm * T::TM * 32 + a * 32 + frow;
-                u32x4 v = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * swz<T::BK>(r, seg));
-                v ^= centre;
-                fa[buf][a] = __builtin_bit_cast(i32x4, v);
-            }
+        for (int a = 0; a < T::TM; ++a) {
+            const int r = wm * T::TM * 32 + a * 32 + frow;
+            fa[buf][a] = *reinterpret_cast<const u32x4*>(sa + r * T::BK + 16 * swz<T::BK>(r, seg));
+        }
 #pragma unroll
-            for (int b = 0; b < T::TN; ++b) {
-                const int r = wn * T::TN * 32 + b * 32 + frow;
-                fb[buf][b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * swz<T::BK>(r, seg));
-            }
-        };
-        read_frags(0, 0);
+        for (int b = 0; b < T::TN; ++b) {
+            const int r = wn * T::TN * 32 + b * 32 + frow;
+            fb[buf][b] = *reinterpret_cast<const i32x4*>(sb + r * T::BK + 16 * swz<T::BK>(r, seg));
+        }
+    };
+    // One k-step of MFMAs (centred A fragments ac, B buffer buf) with loads
+    // lo .. hi-1 of tile t placed between them, one after each MFMA (VMEM
+    // and MFMA scheduling groups).
+    auto mfma_step = [&](const i32x4 (&ac)[T::TM], int buf, uint32_t t, int lo, int hi) {
+        constexpr int kMfma = T::TM * T::TN;
+#pragma unroll
+        for (int a = 0; a < T::TM; ++a)
+#pragma unroll
+            for (int b = 0; b < T::TN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[a], fb[buf][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int i = lo; i < hi; ++i) issue_one(t, i);
+#pragma unroll
+        for (int j = 0; j < hi - lo; ++j) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
+        }
+#pragma unroll
+        for (int j = hi - lo; j < kMfma; ++j) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // First load of tile t_next issued in k-step j.
+    auto first_load = [](int j) {
+        return j < T::ISSUE_STEPS ? j * T::LOADS / T::ISSUE_STEPS : T::LOADS;
+    };
+
+    if (ktiles > 0) {
+#pragma unroll
+        for (int p = 0; p < T::STAGES - 1; ++p)
+#pragma unroll
+            for (int i = 0; i < T::LOADS; ++i) issue_one(p, i);
+    }
+
+    for (uint32_t u = 0; u < ktiles; ++u) {
+        // Tiles u+1 .. u+STAGES-2 (LOADS loads each) were issued after tile
+        // u and loads complete in order, so tile u has landed once at most
+        // that many of this wave's loads are outstanding.  The barrier then
+        // makes every wave's part visible and frees the slot of tile u-1
+        // (every wave's reads of it have returned: the last MFMAs of tile
+        // u-1 waited for them), which is refilled with tile u+STAGES-1
+        // while tile u is consumed.
+        wait_vmcnt<(T::STAGES - 2) * T::LOADS>();
+        ring_barrier();
+
+        // Per k-step: centre the A fragments, read the fragments of the next
+        // step, then the MFMAs with this step's share of the next tile's
+        // loads between them (ISSUE_STEPS).  A wave issuing a tile's loads
+        // back to back waits on the address unit with no MFMA to run
+        // (measured: about 40% of the loop); between MFMAs the waits overlap
+        // them.  The scheduling barriers keep this order.
+        const uint32_t t_next = u + T::STAGES - 1;
+        read_frags(u, 0, 0);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            if (ks + 1 < KS) read_frags(ks + 1, (ks + 1) & 1);
+            i32x4 a_c[T::TM];
 #pragma unroll
-            for (int a = 0; a < T::TM; ++a)
-#pragma unroll
-                for (int b = 0; b < T::TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks & 1][a], fb[ks & 1][b],
-                                                                      acc[a][b], 0, 0, 0);
+            for (int a = 0; a < T::TM; ++a) a_c[a] = __builtin_bit_cast(i32x4, fa[ks & 1][a] ^ centre);
+            __builtin_amdgcn_sched_barrier(0);
+            if (ks + 1 < KS) read_frags(u, ks + 1, (ks + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_step(a_c, ks & 1, t_next, first_load(ks), first_load(ks + 1));
         }
     }
+    // Loads past the last tile may still be landing in LDS.
+    wait_vmcnt<0>();
 
     epi_wave<MODE, GATHER, T::TM, T::TN>(e, tl.split, acc, m0 + wm * T::TM * 32,
                                           n0 + wn * T::TN * 32, lane);
@@ -919,6 +963,9 @@ using Ring8w128x256K128S3 = Ring<4, 2, 1, 4, 3, 128>;   // 8 waves, 144 KiB
 using Ring8w256x256S4 = Ring<4, 2, 2, 4, 4>;            // 8 waves, 128 KiB
 using Ring8w256x256K128S2 = Ring<4, 2, 2, 4, 2, 128>;   // 8 waves, 128 KiB
 using Ring256x256K128S2 = Ring<2, 2, 4, 4, 2, 128>;     // 4 waves of 128 x 128, 128 KiB
+// Two workgroups per CU (64 KiB each): the waves sharing a SIMD belong to
+// different workgroups, so one's barrier does not idle the other.
+using Ring128x128K128S2 = Ring<4, 1, 1, 4, 2, 128>;
 using Roles256x256A5B4 = Roles<2, 2, 4, 4, 5, 4>;       // 80 + 64 KiB
 using Roles128x256A10B4 = Roles<2, 2, 2, 4, 10, 4>;     // 80 + 64 KiB
 using Reg128x256 = Tile<2, 2, 2, 4, 128>;
@@ -931,6 +978,7 @@ struct VariantInfo {
     Kind kind;
     uint32_t bm, bn, bk;
     pir_status (*launch)(const Gemm&, hipStream_t);
+    uint32_t per_cu;        // workgroups resident per CU (LDS-limited ring variants)
 };
 
 const VariantInfo kVariants[] = {
@@ -947,6 +995,7 @@ const VariantInfo kVariants[] = {
     {"reg_128x256", kReg, 128, 256, 128, launch_reg<Reg128x256>},
     {"reg_128x128", kReg, 128, 128, 128, launch_reg<Reg128x128>},
     {"few", kFew, 0, 0, 0, nullptr},   // dot4 stream, batches of at most kFewMax
+    {"ring_128x128_k128_s2", kRing, 128, 128, 128, launch_ring<Ring128x128K128S2>, 2},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
@@ -986,9 +1035,10 @@ struct SplitPlan {
     uint32_t splits, kts;
 };
 
-// Split-K plan for a ring variant.  Ring workgroups hold 128-144 KiB of LDS,
-// one per CU, so a launch runs in ceil(tiles * S / CUs) rounds of 1/S of the
-// K range each; pick the S (up to kMaxSplits, at least two k-tiles per
+// Split-K plan for a ring variant.  LDS lets one or two ring workgroups
+// (per_cu) reside on a CU, so a launch runs in ceil(tiles * S / slots)
+// rounds of 1/S of the K range each, slots = CUs * per_cu; pick the S (up
+// to kMaxSplits, at least two k-tiles per
 // piece) that minimises that time, with a small charge per piece for the
 // partials and the pipeline fill, considered only below two rounds of
 // tiles.  The field form also caps each piece at kExactSpan columns.
@@ -997,12 +1047,13 @@ SplitPlan plan_splits(uint32_t M, uint32_t N, uint32_t C, const VariantInfo& vi,
     if (vi.kind != kRing || ktiles == 0) return {1u, ktiles};
     const uint64_t tiles = (uint64_t)ceil_div(M, vi.bm) * ceil_div(N, vi.bn);
     const uint32_t lo = exact ? ceil_div(ktiles, kExactSpan / vi.bk) : 1u;
+    const uint64_t slots = (uint64_t)g_cus * std::max(1u, vi.per_cu);
     uint32_t best = lo;
-    if (tiles < 2ull * g_cus) {
+    if (tiles < 2ull * slots) {
         const uint32_t hi = std::max(lo, std::min(kMaxSplits, ktiles / 2));
         double best_t = 1e30;
         for (uint32_t sp = lo; sp <= hi; ++sp) {
-            const double t = (double)ceil_div(tiles * sp, g_cus) / sp + 0.005 * sp;
+            const double t = (double)ceil_div(tiles * sp, slots) / sp + 0.005 * sp;
             if (t < best_t) {
                 best_t = t;
                 best = sp;
@@ -1031,7 +1082,8 @@ uint64_t worst_split_rows(const pir_db_t* db, uint32_t N) {
         const uint32_t nt = N / vi.bn;
         const uint32_t mt_all = ceil_div(R, vi.bm);
         // Row counts where the plan may split for occupancy, then R itself.
-        const uint32_t mt_hi = std::min<uint64_t>(mt_all, (2ull * g_cus + nt - 1) / nt);
+        const uint64_t slots = (uint64_t)g_cus * std::max(1u, vi.per_cu);
+        const uint32_t mt_hi = std::min<uint64_t>(mt_all, (2ull * slots + nt - 1) / nt);
         for (uint32_t mt = 1; mt <= mt_hi + 1 && mt <= mt_all; ++mt) {
             const uint32_t M = mt == mt_all ? R : mt * vi.bm;
             for (int x = 0; x <= (exact_ok ? 1 : 0); ++x) {
@@ -1093,6 +1145,7 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Ring8w256x256S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring8w256x256K128S2>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring256x256K128S2>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring128x128K128S2>()) != PIR_OK) return st;
     if ((st = set_roles_lds<Roles256x256A5B4>()) != PIR_OK) return st;
     return set_roles_lds<Roles128x256A10B4>();
 }
