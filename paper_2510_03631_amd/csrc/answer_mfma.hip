@@ -93,11 +93,14 @@ __global__ void k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
 // query matrix is Q[j * ldj + b * ldb].  Loads are coalesced along b for the
 // row-major layout (ldb == 1: a wave reads 64 consecutive words of one row)
 // and along j for the query-major one (QMAJOR, ldj == 1).  The tile goes
-// through LDS with rows padded to 129 words, so that both the store (64
-// lanes, one j, consecutive b) and the transposed read (64 lanes, consecutive
-// b, one j) hit 64 distinct banks.  Then thread (b, limb) writes the 128
-// limb bytes of its QL row as eight 16-byte stores (one full 128-byte run
-// per row), and the limb-0 threads add the exact column sums.
+// through LDS with rows padded to 129 words, so that the stores hit 64
+// distinct banks.  The block's QL rows (b0/32)*128 .. +255 are consecutive
+// 128-byte runs of the tiled layout; in the write phase lane l of a wave
+// packs and stores 16-byte chunk l % 8 of row l / 8, so one store covers
+// eight whole rows (1 KiB).  (Storing a thread's whole row as eight 16-byte
+// pieces made every store touch 64 lines: 1.6 TB/s at 128 queries.)  The
+// rows of limb 0 also sum their words: three lane shuffles combine the
+// eight chunks of a row, and one lane adds the exact column sum.
 constexpr int kIngJ = 128;
 constexpr int kIngB = 64;
 
@@ -174,17 +177,18 @@ __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, 
         }
     }
     __syncthreads();
-    const int bl = t & (kIngB - 1);
-    const int limb = t >> 6;
-    const uint32_t b = b0 + bl;
-    if (b >= Bp) return;                       // no QL row (one 32-query group only)
-    const bool live = b < B;
-    const uint32_t n = (b / 32u) * 128u + (uint32_t)limb * 32u + (b % 32u);
-    u32x4* dst = reinterpret_cast<u32x4*>(QL + ql_row(n, Cp) + ql_col(j0));
-    u64 sum = 0;
+    const int e = t & 7;                       // 16-byte chunk of the row
+    const uint32_t n0 = (b0 / 32u) * 128u;
 #pragma unroll 2
-    for (int e = 0; e < kIngJ / 16; ++e) {
+    for (int rnd = 0; rnd < 8; ++rnd) {
+        const int R = rnd * 32 + (t >> 3);     // row of the block, 0..255
+        const int limb = rnd & 3;              // (R % 128) / 32
+        const int bl = (R >> 7) * 32 + (R & 31);
+        const uint32_t b = b0 + bl;
+        if (b >= Bp) continue;                 // uniform per wave: no QL row
+        const bool live = b < B;
         uint32_t w[4];
+        u64 sum = 0;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             uint32_t word = 0;
@@ -192,16 +196,22 @@ __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, 
             for (int y = 0; y < 4; ++y) {
                 const int jl = 16 * e + 4 * x + y;
                 const uint32_t v = s[bl][jl];
-                sum += v;
+                if (limb == 0) sum += v;
                 const uint32_t byte =
                     (live && j0 + jl < C) ? (((v >> (8 * limb)) & 0xFFu) ^ 0x80u) : 0u;
                 word |= byte << (8 * y);
             }
             w[x] = word;
         }
-        dst[e] = u32x4{w[0], w[1], w[2], w[3]};
+        *reinterpret_cast<u32x4*>(QL + ql_row(n0 + R, Cp) + ql_col(j0) + 16 * e) =
+            u32x4{w[0], w[1], w[2], w[3]};
+        if (limb == 0) {
+            sum += __shfl_xor(sum, 1);
+            sum += __shfl_xor(sum, 2);
+            sum += __shfl_xor(sum, 4);
+            if (e == 0 && live) atomicAdd(&colsum[b], sum);
+        }
     }
-    if (limb == 0 && live) atomicAdd(&colsum[b], sum);
 }
 
 // ---------------------------------------------------------------- epilogue
