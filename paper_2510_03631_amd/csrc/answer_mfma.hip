@@ -50,7 +50,11 @@
 //
 // QL row index of (query b, limb k): n = (b / 32) * 128 + k * 32 + (b % 32),
 // so the four limbs of a query land in the same lane of four adjacent 32x32
-// output tiles and the epilogue combines them in registers.  QL is stored in
+// output tiles and the epilogue combines them in registers.  Batches of at
+// most 16 queries may use the narrow layout n = (b / 8) * 32 + k * 8 + b % 8
+// instead: one 32-column tile holds all four limbs of 8 queries, so a batch
+// of 8 is not padded to 32 queries; the epilogue then combines the limbs
+// of a query across lanes c, c+8, c+16, c+24 with two shuffles.  QL is stored in
 // 4 KiB tiles of 32 rows x 128 bytes (tile (n/32, k/128) at
 // ((n/32) * Cp/128 + k/128) * 4096, row n%32 at 128 (n%32) within it): the
 // ingest writes whole tiles and a 1 KiB block of a GEMM k-tile is contiguous.
@@ -94,8 +98,8 @@ __global__ void k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
 // row-major layout (ldb == 1: a wave reads 64 consecutive words of one row)
 // and along j for the query-major one (QMAJOR, ldj == 1).  The tile goes
 // through LDS with rows padded to 129 words, so that the stores hit 64
-// distinct banks.  The block's QL rows (b0/32)*128 .. +255 are consecutive
-// 128-byte runs of the tiled layout; in the write phase lane l of a wave
+// distinct banks.  The block's QL rows 4*b0 .. 4*b0+255 (either layout)
+// are consecutive 128-byte runs of the tiled layout; in the write phase lane l of a wave
 // packs and stores 16-byte chunk l % 8 of row l / 8, so one store covers
 // eight whole rows (1 KiB).  (Storing a thread's whole row as eight 16-byte
 // pieces made every store touch 64 lines: 1.6 TB/s at 128 queries.)  The
@@ -112,7 +116,7 @@ template <bool QMAJOR, bool VEC>
 __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, uint64_t ldj,
                                                 uint64_t ldb, uint32_t C, uint32_t B, uint32_t Bp,
                                                 uint32_t Cp, int8_t* __restrict__ QL,
-                                                u64* __restrict__ colsum) {
+                                                u64* __restrict__ colsum, bool narrow) {
     __shared__ uint32_t s[kIngB][kIngJ + 1];
     const int t = threadIdx.x;
     // Query blocks vary fastest across the grid, so the blocks that read one
@@ -178,14 +182,16 @@ __global__ __launch_bounds__(256) void k_ingest(const uint32_t* __restrict__ Q, 
     }
     __syncthreads();
     const int e = t & 7;                       // 16-byte chunk of the row
-    const uint32_t n0 = (b0 / 32u) * 128u;
+    const uint32_t n0 = 4u * b0;               // first QL row of the block, either layout
 #pragma unroll 2
     for (int rnd = 0; rnd < 8; ++rnd) {
         const int R = rnd * 32 + (t >> 3);     // row of the block, 0..255
-        const int limb = rnd & 3;              // (R % 128) / 32
-        const int bl = (R >> 7) * 32 + (R & 31);
+        // Wide: R = 128 g + 32 limb + b % 32; narrow: R = 32 g + 8 limb + b % 8.
+        // Either way limb and the 8-query group of b are uniform per wave.
+        const int limb = narrow ? (R & 31) >> 3 : (R & 127) >> 5;
+        const int bl = narrow ? (R >> 5) * 8 + (R & 7) : (R >> 7) * 32 + (R & 31);
         const uint32_t b = b0 + bl;
-        if (b >= Bp) continue;                 // uniform per wave: no QL row
+        if (b >= Bp) continue;                 // uniform per wave (Bp % 8 == 0): no QL row
         const bool live = b < B;
         uint32_t w[4];
         u64 sum = 0;
@@ -240,32 +246,40 @@ __device__ inline u64 limb64(int32_t v) {
     return v == INT32_MIN ? (1ull << 31) : (u64)(int64_t)v;
 }
 
-// Output element (local row i, query b) from its four limb products.
+// Output element (local row i, query b) from its limb combination
+// x = sum_k 2^(8k) P_k (exact; only x mod 2^32 matters in the 32-bit modes).
 template <int MODE, bool GATHER>
-__device__ inline void epi_store(const Epi& e, uint32_t split, uint32_t i, uint32_t b, int32_t p0,
-                                 int32_t p1, int32_t p2, int32_t p3) {
+__device__ inline void epi_put(const Epi& e, uint32_t split, uint32_t i, uint32_t b, u64 x) {
     if (i >= e.M || b >= e.B) return;
     if (MODE == kFinal32 || MODE == kFinalModP) {
         const uint32_t r = GATHER ? e.rows[i] : i;
         if (r >= e.R) return;
         uint32_t* dst = e.out + (uint64_t)r * e.o_ldr + (uint64_t)b * e.o_ldb;
-        if (MODE == kFinal32) {
-            *dst = (uint32_t)p0 + ((uint32_t)p1 << 8) + ((uint32_t)p2 << 16) +
-                   ((uint32_t)p3 << 24) + colterm32(e, b) + kCentreWord * e.rowsum[r];
-        } else {
-            const u64 v = limb64(p0) + (limb64(p1) << 8) + (limb64(p2) << 16) +
-                          (limb64(p3) << 24) + colterm64(e, b) + (u64)kCentreWord * e.rowsum[r];
-            *dst = (uint32_t)(v % e.p);
-        }
+        if (MODE == kFinal32)
+            *dst = (uint32_t)x + colterm32(e, b) + kCentreWord * e.rowsum[r];
+        else
+            *dst = (uint32_t)((x + colterm64(e, b) + (u64)kCentreWord * e.rowsum[r]) % e.p);
     } else {
         const uint64_t at = ((uint64_t)split * e.M + i) * e.B + b;
         if (MODE == kPart32)
-            static_cast<uint32_t*>(e.part)[at] = (uint32_t)p0 + ((uint32_t)p1 << 8) +
-                                                 ((uint32_t)p2 << 16) + ((uint32_t)p3 << 24);
+            static_cast<uint32_t*>(e.part)[at] = (uint32_t)x;
         else
-            static_cast<u64*>(e.part)[at] =
-                limb64(p0) + (limb64(p1) << 8) + (limb64(p2) << 16) + (limb64(p3) << 24);
+            static_cast<u64*>(e.part)[at] = x;
     }
+}
+
+// Limb combination of four limb products (wide layout).
+template <int MODE, bool GATHER>
+__device__ inline void epi_store(const Epi& e, uint32_t split, uint32_t i, uint32_t b, int32_t p0,
+                                 int32_t p1, int32_t p2, int32_t p3) {
+    if (MODE == kFinal32 || MODE == kPart32)
+        epi_put<MODE, GATHER>(e, split, i, b,
+                              (uint32_t)p0 + ((uint32_t)p1 << 8) + ((uint32_t)p2 << 16) +
+                                  ((uint32_t)p3 << 24));
+    else
+        epi_put<MODE, GATHER>(e, split, i, b,
+                              limb64(p0) + (limb64(p1) << 8) + (limb64(p2) << 16) +
+                                  (limb64(p3) << 24));
 }
 
 // Write a wave's accumulators through the epilogue: the four limb tiles of
@@ -284,6 +298,41 @@ __device__ inline void epi_wave(const Epi& e, uint32_t split, const i32x16 (&acc
                 const uint32_t i = m_base + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
                 epi_store<MODE, GATHER>(e, split, i, bq, acc[a][4 * g][v], acc[a][4 * g + 1][v],
                                         acc[a][4 * g + 2][v], acc[a][4 * g + 3][v]);
+            }
+        }
+    }
+}
+
+// Narrow layout: in 32-column tile t of a wave, lane column c holds limb
+// c / 8 of query n_base / 4 + 8 t + c % 8 (C layout as above).  The four
+// limbs of a query sit in lanes c, c ^ 8, c ^ 16, c ^ 24 of the same half
+// wave; two xor shuffles add the shifted products and lanes with c < 8
+// store.
+template <int MODE, bool GATHER, int TM, int TN>
+__device__ inline void epi_wave_narrow(const Epi& e, uint32_t split, const i32x16 (&acc)[TM][TN],
+                                       uint32_t m_base, uint32_t n_base, int lane) {
+    const int c = lane & 31;
+    const int limb = c >> 3;
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+        const uint32_t bq = n_base / 4u + 8u * t + (uint32_t)(c & 7);
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const uint32_t i = m_base + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+                u64 x;
+                if (MODE == kFinal32 || MODE == kPart32) {
+                    uint32_t y = (uint32_t)acc[a][t][v] << (8 * limb);
+                    y += __shfl_xor(y, 8);
+                    y += __shfl_xor(y, 16);
+                    x = y;
+                } else {
+                    x = limb64(acc[a][t][v]) << (8 * limb);
+                    x += __shfl_xor(x, 8);
+                    x += __shfl_xor(x, 16);
+                }
+                if (limb == 0) epi_put<MODE, GATHER>(e, split, i, bq, x);
             }
         }
     }
@@ -509,9 +558,10 @@ __device__ inline void ring_barrier() {
 // staging), into a ring of STAGES k-tiles of BK bytes, so STAGES-1 tiles are
 // in flight while one is consumed.  Centring of D (xor 0x80) is applied to
 // the A fragments in registers.
-template <int WM_, int WN_, int TM_, int TN_, int STAGES_, int BK_ = 64>
+template <int WM_, int WN_, int TM_, int TN_, int STAGES_, int BK_ = 64, bool NARROW_ = false>
 struct Ring {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, STAGES = STAGES_;
+    static constexpr bool NARROW = NARROW_;              // narrow QL layout (8 queries per tile)
     static constexpr int NW = WM * WN;                   // waves per workgroup
     static constexpr int THREADS = 64 * NW;
     static constexpr int BK = BK_;                       // k bytes per stage: 64 or 128
@@ -527,7 +577,7 @@ struct Ring {
     static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
     static_assert(BK == 64 || BK == 128, "64- or 128-byte stages");
     static_assert(NW == 4 || NW == 8, "four or eight waves");
-    static_assert(TN % 4 == 0, "a wave covers whole groups of four limbs");
+    static_assert(NARROW || TN % 4 == 0, "a wave covers whole groups of four limbs");
     static_assert(BLOCKS % NW == 0, "blocks split evenly over waves");
     static_assert(A_BLOCKS % NW == 0, "a wave's first A_LOADS loads carry D rows");
     static constexpr int A_LOADS = A_BLOCKS / NW;
@@ -538,8 +588,6 @@ struct Ring {
     static constexpr int KS = BK / 32;
     static constexpr int FIT = (LOADS + TM * TN - 1) / (TM * TN);
     static constexpr int ISSUE_STEPS = STAGES > 2 ? KS : (FIT < KS ? FIT : KS);
-    static_assert((LOADS + ISSUE_STEPS - 1) / ISSUE_STEPS <= TM * TN,
-                  "a k-step's share of the loads fits between its MFMAs");
     static_assert((STAGES - 2) * LOADS < 64, "vmcnt range");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
@@ -640,7 +688,8 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     };
     // One k-step of MFMAs (centred A fragments ac, B buffer buf) with loads
     // lo .. hi-1 of tile t placed between them, one after each MFMA (VMEM
-    // and MFMA scheduling groups).
+    // and MFMA scheduling groups); narrow tiles, with more loads than MFMAs,
+    // issue the rest after the last MFMA.
     auto mfma_step = [&](const i32x4 (&ac)[T::TM], int buf, uint32_t t, int lo, int hi) {
         constexpr int kMfma = T::TM * T::TN;
 #pragma unroll
@@ -650,13 +699,16 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
                 acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[a], fb[buf][b], acc[a][b], 0, 0, 0);
 #pragma unroll
         for (int i = lo; i < hi; ++i) issue_one(t, i);
+        const int paired = hi - lo < kMfma ? hi - lo : kMfma;
 #pragma unroll
-        for (int j = 0; j < hi - lo; ++j) {
+        for (int j = 0; j < paired; ++j) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
         }
 #pragma unroll
-        for (int j = hi - lo; j < kMfma; ++j) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        for (int j = paired; j < kMfma; ++j) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+        for (int j = paired; j < hi - lo; ++j) __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
         __builtin_amdgcn_sched_barrier(0);
     };
     // First load of tile t_next issued in k-step j.
@@ -704,8 +756,12 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     // Loads past the last tile may still be landing in LDS.
     wait_vmcnt<0>();
 
-    epi_wave<MODE, GATHER, T::TM, T::TN>(e, tl.split, acc, m0 + wm * T::TM * 32,
-                                          n0 + wn * T::TN * 32, lane);
+    if constexpr (T::NARROW)
+        epi_wave_narrow<MODE, GATHER, T::TM, T::TN>(e, tl.split, acc, m0 + wm * T::TM * 32,
+                                                     n0 + wn * T::TN * 32, lane);
+    else
+        epi_wave<MODE, GATHER, T::TM, T::TN>(e, tl.split, acc, m0 + wm * T::TM * 32,
+                                              n0 + wn * T::TN * 32, lane);
 }
 
 // ---------------------------------------------------------------- GEMM, split load roles
@@ -976,6 +1032,10 @@ using Ring256x256K128S2 = Ring<2, 2, 4, 4, 2, 128>;     // 4 waves of 128 x 128,
 // Two workgroups per CU (64 KiB each): the waves sharing a SIMD belong to
 // different workgroups, so one's barrier does not idle the other.
 using Ring128x128K128S2 = Ring<4, 1, 1, 4, 2, 128>;
+// Narrow layout (8 queries per 32-column tile), one column tile per batch.
+using Narrow256x32K128S4 = Ring<4, 1, 2, 1, 4, 128, true>;    // <= 8 queries, 144 KiB
+using Narrow256x64K128S4 = Ring<8, 1, 1, 2, 4, 128, true>;    // <= 16 queries, 160 KiB
+using Narrow128x32K128S6 = Ring<4, 1, 1, 1, 6, 128, true>;    // <= 8 queries, 120 KiB
 using Roles256x256A5B4 = Roles<2, 2, 4, 4, 5, 4>;       // 80 + 64 KiB
 using Roles128x256A10B4 = Roles<2, 2, 2, 4, 10, 4>;     // 80 + 64 KiB
 using Reg128x256 = Tile<2, 2, 2, 4, 128>;
@@ -989,6 +1049,7 @@ struct VariantInfo {
     uint32_t bm, bn, bk;
     pir_status (*launch)(const Gemm&, hipStream_t);
     uint32_t per_cu;        // workgroups resident per CU (LDS-limited ring variants)
+    bool narrow;            // narrow QL layout: all queries in one column tile
 };
 
 const VariantInfo kVariants[] = {
@@ -1006,6 +1067,9 @@ const VariantInfo kVariants[] = {
     {"reg_128x128", kReg, 128, 128, 128, launch_reg<Reg128x128>},
     {"few", kFew, 0, 0, 0, nullptr},   // dot4 stream, batches of at most kFewMax
     {"ring_128x128_k128_s2", kRing, 128, 128, 128, launch_ring<Ring128x128K128S2>, 2},
+    {"narrow_256x32_k128_s4", kRing, 256, 32, 128, launch_ring<Narrow256x32K128S4>, 1, true},
+    {"narrow_256x64_k128_s4", kRing, 256, 64, 128, launch_ring<Narrow256x64K128S4>, 1, true},
+    {"narrow_128x32_k128_s6", kRing, 128, 32, 128, launch_ring<Narrow128x32K128S6>, 1, true},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
@@ -1015,12 +1079,19 @@ bool ring_ok(const pir_db_t* db) { return db->aligned && (db->cols % 16 == 0); }
 
 uint32_t padded_batch(uint32_t B) { return B <= 32u ? 32u : (B + 63u) / 64u * 64u; }
 
+// Queries a variant's QL layout holds for batch B: narrow variants hold one
+// column tile (BN / 4 queries), the others B padded to 32 or to 64.
+uint32_t layout_batch(const VariantInfo& vi, uint32_t B) {
+    return vi.narrow ? vi.bn / 4u : padded_batch(B);
+}
+
 bool variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
     if (v == 0) return true;
     if (v >= kNumVariants) return false;
     const VariantInfo& vi = kVariants[v];
     if (vi.kind == kFew) return B <= kFewMax;
     if (vi.kind != kReg && !ring_ok(db)) return false;
+    if (vi.narrow) return 4u * B <= vi.bn;
     return (4u * padded_batch(B)) % vi.bn == 0;
 }
 
@@ -1075,20 +1146,24 @@ SplitPlan plan_splits(uint32_t M, uint32_t N, uint32_t C, const VariantInfo& vi,
 }
 
 struct BatchLayout {
-    uint32_t Bp, N, Cp;
+    uint32_t Bp, N, Cp;     // queries in the QL layout, its limb rows, padded columns
     size_t colsum_off, part_off, total;
 };
 
-// Largest (splits x output rows) of any split-K plan for N limb columns:
-// every ring variant valid for N, every output row count up to R (gathered
-// calls have fewer rows, and so may split more), both forms.
-uint64_t worst_split_rows(const pir_db_t* db, uint32_t N) {
+// Largest (splits x output rows) of any split-K plan for the batches whose
+// wide layout has N limb columns: every ring variant valid for them (narrow
+// variants, one column tile, for N = 128: batches of at most 32), every
+// output row count up to R (gathered calls have fewer rows, and so may split
+// more), both forms.
+uint64_t worst_split_rows(const pir_db_t* db, uint32_t N_wide) {
     const uint32_t R = (uint32_t)db->rows, C = (uint32_t)db->cols;
     const bool exact_ok = C <= kMaxExactCols;
     uint64_t worst = 0;   // splits x rows
     for (uint32_t v = 1; v < kNumVariants; ++v) {
         const VariantInfo& vi = kVariants[v];
-        if (vi.kind != kRing || N % vi.bn) continue;
+        if (vi.kind != kRing) continue;
+        if (vi.narrow ? N_wide != 128u : N_wide % vi.bn != 0) continue;
+        const uint32_t N = vi.narrow ? vi.bn : N_wide;
         const uint32_t nt = N / vi.bn;
         const uint32_t mt_all = ceil_div(R, vi.bm);
         // Row counts where the plan may split for occupancy, then R itself.
@@ -1127,15 +1202,18 @@ size_t partial_bound(const pir_db_t* db, uint32_t B, uint32_t N) {
     return worst ? round_up((size_t)worst * B * 8, kWsAlign) : 0;
 }
 
-// Workspace: limb planes, exact column sums, split-K partials.
-BatchLayout batch_layout(const pir_db_t* db, uint32_t B) {
+// Workspace: limb planes, exact column sums, split-K partials.  The
+// partial bound covers every variant (it depends on the wide layout only),
+// and the wide layout's limb planes are the larger, so mfma_workspace_bytes
+// uses the wide layout.
+BatchLayout batch_layout(const pir_db_t* db, uint32_t B, const VariantInfo& vi) {
     BatchLayout L;
-    L.Bp = padded_batch(B);
+    L.Bp = layout_batch(vi, B);
     L.N = 4u * L.Bp;
     L.Cp = (uint32_t)round_up(db->cols, kKPad);
     L.colsum_off = round_up((size_t)L.N * L.Cp, kWsAlign);
     L.part_off = L.colsum_off + round_up((size_t)L.Bp * 8, kWsAlign);
-    L.total = L.part_off + partial_bound(db, B, L.N);
+    L.total = L.part_off + partial_bound(db, B, 4u * padded_batch(B));
     return L;
 }
 
@@ -1156,6 +1234,9 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Ring8w256x256K128S2>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring256x256K128S2>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring128x128K128S2>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Narrow256x32K128S4>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Narrow256x64K128S4>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Narrow128x32K128S6>()) != PIR_OK) return st;
     if ((st = set_roles_lds<Roles256x256A5B4>()) != PIR_OK) return st;
     return set_roles_lds<Roles128x256A10B4>();
 }
@@ -1170,7 +1251,7 @@ bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
 
 size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B) {
     if (B == 0) return 0;
-    return std::max(batch_layout(db, B).total, few_workspace_bytes(db, B));
+    return std::max(batch_layout(db, B, kVariants[kVarRing128]).total, few_workspace_bytes(db, B));
 }
 
 pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
@@ -1194,7 +1275,8 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
         return PIR_ERR_UNSUPPORTED;   // field form beyond kFewMax queries needs the ring kernels
     if (kVariants[v].kind == kFew) return few_answer_batch(db, io, B, modulus, ws, ws_bytes, s);
 
-    const BatchLayout L = batch_layout(db, B);
+    const VariantInfo& vi = kVariants[v];
+    const BatchLayout L = batch_layout(db, B, vi);
     if (!ws || ws_bytes < L.total || ((uintptr_t)ws % kWsAlign)) return PIR_ERR_WORKSPACE;
     uint8_t* base = static_cast<uint8_t*>(ws);
     int8_t* QL = reinterpret_cast<int8_t*>(base);
@@ -1208,7 +1290,8 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
     const bool vec = ((uintptr_t)io.Q % 16 == 0) &&
                      (qmajor ? (io.q_ldb % 4 == 0 && C % 4 == 0) : (io.q_ldj % 4 == 0 && B % 4 == 0));
 #define PIR_INGEST(QM, V)                                                                  \
-    k_ingest<QM, V><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Bp, L.Cp, QL, colsum)
+    k_ingest<QM, V><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Bp, L.Cp, QL, colsum, \
+                                       vi.narrow)
     if (qmajor) {
         if (vec) PIR_INGEST(true, true); else PIR_INGEST(true, false);
     } else {
@@ -1219,7 +1302,6 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
 
     const uint32_t M = rows ? m : (uint32_t)db->rows;
     if (M == 0) return PIR_OK;
-    const VariantInfo& vi = kVariants[v];
     const SplitPlan sp = plan_splits(M, L.N, C, vi, exact);
     if (sp.splits > 1 && L.part_off + (size_t)sp.splits * M * B * 8 > L.total)
         return PIR_ERR_WORKSPACE;   // cannot happen: the layout bounds every plan

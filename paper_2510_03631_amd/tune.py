@@ -62,7 +62,7 @@ def tune_database(db: Database, batches, reps: int = 5, log=print, modulus: int 
                 fn = lambda: db.answer_batch(Q, out=out, ws=ws)
         times = {}
         for v, name in enumerate(names):
-            if v == 0 or (modulus and B and not name.startswith(("ring", "few"))):
+            if v == 0 or (modulus and B and not name.startswith(("ring", "narrow", "few"))):
                 continue
             try:
                 db.set_variant(B, v)

@@ -70,6 +70,31 @@ def test_modp_every_variant(qp):
             assert np.array_equal(to_host_u32(db.answer_batch_modp(to_dev_u32(Q), P)), exp), name
 
 
+@pytest.mark.parametrize("R,C,B", [(300, 4096, 3), (517, 8192, 8), (64, 2048, 16),
+                                   (40, (1 << 17) + 4096, 8)])
+def test_modp_small_batch_variants(qp, R, C, B):
+    # Every variant that serves a small batch (dot4 stream, narrow and wide
+    # matrix-core layouts, split-K when C > 2^17) gives the oracle's value.
+    from paper_2510_03631_amd._lib import variant_names
+    g = np.random.default_rng(R + C + B)
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    Q = workload.uniform_mod(g, (C, B), P)
+    exp = oracle.answer_batch_mod(D, Q, P)
+    tried = 0
+    with qp.Database(to_dev_u8(D)) as db:
+        for v, name in enumerate(variant_names(B)):
+            if not name.startswith(("ring", "narrow", "few")):
+                continue
+            try:
+                db.set_variant(B, v)
+            except qp.PirError:
+                continue
+            banner(f"modp small batch R={R} C={C} B={B} {name}")
+            assert np.array_equal(to_host_u32(db.answer_batch_modp(to_dev_u32(Q), P)), exp), name
+            tried += 1
+    assert tried >= 3
+
+
 def test_modp_rows_longer_than_one_exact_span(qp):
     # C > 2^17: every accumulation covers at most 2^17 columns (split-K).
     R, C, B = 40, (1 << 17) + 4096, 5

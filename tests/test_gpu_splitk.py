@@ -21,11 +21,12 @@ def qp(gpu):
 
 
 def _ring_variants(qp, B):
-    return [(v, n) for v, n in enumerate(qp.variant_names(B)) if n.startswith("ring")]
+    return [(v, n) for v, n in enumerate(qp.variant_names(B)) if n.startswith(("ring", "narrow"))]
 
 
 @pytest.mark.parametrize("R,C,B", [(1, 131072, 1), (64, 65536, 64), (100, 32768, 1),
-                                   (257, 16384, 200), (5, 8192 + 48, 33)])
+                                   (257, 16384, 200), (5, 8192 + 48, 33), (70, 40960, 8),
+                                   (129, 16384 + 16, 16)])
 def test_few_rows_long_rows(qp, R, C, B):
     g = np.random.default_rng(R + C + B)
     D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
@@ -44,10 +45,10 @@ def test_few_rows_long_rows(qp, R, C, B):
             assert np.array_equal(to_host_u32(db.answer_batch_qmajor(Qtd)), exp.T), name
 
 
-@pytest.mark.parametrize("m", [1, 37, 300])
-def test_incremental_hint_gathered_rows(qp, m):
+@pytest.mark.parametrize("m,n", [(1, 256), (37, 256), (300, 256), (37, 5), (300, 16)])
+def test_incremental_hint_gathered_rows(qp, m, n):
     import torch
-    R, C, n = 4096, 16384, 256
+    R, C = 4096, 16384
     g = np.random.default_rng(m)
     D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
     A = workload.uniform_u32(g, (C, n))
@@ -65,7 +66,7 @@ def test_incremental_hint_gathered_rows(qp, m):
                 db.set_variant(n, v)
             except qp.PirError:
                 continue
-            banner(f"incremental hint m={m} {name}")
+            banner(f"incremental hint m={m} n={n} {name}")
             H.zero_()
             db.hint_update_rows(rows_d, Ad, H)
             Hh = to_host_u32(H)
@@ -83,7 +84,7 @@ def test_workspace_covers_every_plan(qp):
     g = np.random.default_rng(5)
     D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
     with qp.Database(to_dev_u8(D)) as db:
-        for B in (1, 32, 33, 64, 65, 256, 1024):
+        for B in (1, 8, 16, 32, 33, 64, 65, 256, 1024):
             nbytes = db.workspace_bytes(B)
             ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             Q = workload.uniform_u32(g, (C, B))

@@ -31,7 +31,8 @@ def test_single_query_variants(qp, R, C):
 
 
 @pytest.mark.parametrize("R,C,B", [(300, 4096, 64), (257, 1040, 100), (130, 2000, 7),
-                                   (64, 512, 256), (700, 3072, 33)])
+                                   (64, 512, 256), (700, 3072, 33), (500, 4096, 3),
+                                   (300, 1040, 16), (1000, 2048, 9)])
 def test_batch_variants(qp, R, C, B):
     from paper_2510_03631_amd._lib import variant_names
     g = np.random.default_rng(R * 3 + C + B)
