@@ -413,9 +413,27 @@ def profile_mode(args, dev, stream) -> int:
             del a, b
             torch.cuda.empty_cache()
         return 0
-    D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
-    db = qp.Database(D)
-    tune.apply(db)
+    if args.profile == "update":
+        # The refresh workload: 1% of the rows of the 16 GiB database
+        # rewritten, then the incremental hint over those rows.
+        big = workload.CONFIGS["large_b256"]
+        R, C, n = big.rows, big.cols, big.n
+        D = workload.device_db(R, C, workload.SEED_BASE + 4, dev)
+        db = qp.Database(D)
+        tune.apply(db)
+        A = workload.device_u32((C, n), workload.SEED_BASE + 6, dev)
+        H = torch.empty((R, n), dtype=torch.int32, device=dev)
+        ws = db.workspace(n)
+        g = workload.rng(workload.SEED_BASE + 7)
+        m = workload.update_count(R)
+        rows = torch.from_numpy(workload.distinct_rows(g, R, m).view("int32")).to(dev)
+        new = workload.device_db(m, C, workload.SEED_BASE + 8, dev)
+        db.update_rows(rows, new)
+        fn = lambda: db.hint_update_rows(rows, A, H, ws=ws)
+    else:
+        D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
+        db = qp.Database(D)
+        tune.apply(db)
     if args.profile == "answer":
         q = workload.device_u32((C,), workload.SEED_BASE + 2, dev)
         a = torch.empty(R, dtype=torch.int32, device=dev)
@@ -427,7 +445,7 @@ def profile_mode(args, dev, stream) -> int:
         out = torch.empty((R, B), dtype=torch.int32, device=dev)
         ws = db.workspace(B)
         fn = lambda: db.answer_batch(Q, out=out, ws=ws)
-    else:
+    elif args.profile != "update":
         A = workload.device_u32((C, n), workload.SEED_BASE + 4, dev)
         H = torch.empty((R, n), dtype=torch.int32, device=dev)
         ws = db.workspace(n)
@@ -495,7 +513,8 @@ def main() -> int:
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--profile",
                     help="run only one kernel family (for rocprofv3 runs) and exit: answer, "
-                         "batch, hint, calibrate, or chorB / oopB / ftrB with B queries")
+                         "batchB, hint, update (incremental hint, 16 GiB), calibrate, intmm, "
+                         "or chorB / oopB / ftrB with B queries")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
