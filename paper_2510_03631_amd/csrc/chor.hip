@@ -224,7 +224,23 @@ __global__ __launch_bounds__(kThreads) void k_chor_shared(const uint32_t* __rest
         x[2] = need2 ? load_row(r + 2) : u32x4{0, 0, 0, 0};
         x[3] = need3 ? load_row(r + 3) : u32x4{0, 0, 0, 0};
     };
-    auto load_sel = [&](uint32_t blk) -> uint32_t {
+    // Selector words of the wave's G queries for one 32-row block.
+    // * G <= 16: the address is wave-uniform, so these are scalar loads into
+    //   SGPRs and the per-lookup table index is scalar arithmetic.  They are
+    //   loaded at a block's first step; the step's barrier waits on the same
+    //   counter as the LDS writes, so no separate wait is exposed.  Queries
+    //   past B read query B-1's word; their sums are never stored.
+    // * G = 32 would spill SGPRs: lane g holds query g's word (one vector
+    //   load, prefetched a block ahead) and each lookup reads its lane.
+    constexpr bool kScalarSel = G <= 16;
+    auto load_sel = [&](uint32_t blk, uint32_t (&sel)[G]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t b = min(qbase + (uint32_t)g, B - 1u);
+            sel[g] = 32u * blk < rows ? Q[(uint64_t)b * qwords + blk] : 0u;
+        }
+    };
+    auto load_sel_lane = [&](uint32_t blk) -> uint32_t {
         const uint32_t b = qbase + (uint32_t)lane;
         return ((uint32_t)lane < nq && 32u * blk < rows) ? Q[(uint64_t)b * qwords + blk] : 0u;
     };
@@ -233,13 +249,18 @@ __global__ __launch_bounds__(kThreads) void k_chor_shared(const uint32_t* __rest
     u32x4 xa[4], xb[4];
     load_step(0, xa);
     load_step(1, xb);
-    uint32_t qv = 0, qv_next = load_sel(r0 / 32u);
+    uint32_t qv[kScalarSel ? G : 1];
+    uint32_t qlane = 0, qlane_next = kScalarSel ? 0u : load_sel_lane(r0 / 32u);
 
     auto step = [&](uint32_t st, u32x4 (&x)[4]) {
         const int buf = st & 1;
         if (st % 8u == 0) {
-            qv = qv_next;
-            qv_next = load_sel(r0 / 32u + st / 8u + 1u);
+            if constexpr (kScalarSel) {
+                load_sel(r0 / 32u + st / 8u, qv);
+            } else {
+                qlane = qlane_next;
+                qlane_next = load_sel_lane(r0 / 32u + st / 8u + 1u);
+            }
         }
         const u32x4 lo1 = x[0], lo2 = x[1], lo3 = x[0] ^ x[1];
         const u32x4 hi = wave == 0 ? u32x4{0, 0, 0, 0}
@@ -256,7 +277,9 @@ __global__ __launch_bounds__(kThreads) void k_chor_shared(const uint32_t* __rest
             u32x4 t[8];
 #pragma unroll
             for (int g = 0; g < 8 && g0 + g < G; ++g) {
-                const uint32_t idx = (__builtin_amdgcn_readlane(qv, g0 + g) >> sh) & 15u;
+                const uint32_t word = kScalarSel ? qv[kScalarSel ? g0 + g : 0]
+                                                 : __builtin_amdgcn_readlane(qlane, g0 + g);
+                const uint32_t idx = (word >> sh) & 15u;
                 t[g] = s_tab[buf][idx][lane];
             }
 #pragma unroll
