@@ -163,3 +163,36 @@ def test_open_loop_replay(env):
     assert st["p50_ns"] <= st["p99_ns"] <= st["max_ns"]
     for k, (d, i) in enumerate(zip(which, pick)):
         assert np.array_equal(outs[k], expected[d][i]), k
+
+
+def test_narrow_variants_in_graphs(env):
+    """The narrow-layout kernels inside captured graphs: every database
+    serves batches of up to 4 / 8 / 16 with them, replayed twice with eager
+    work between, and every answer equals the oracle's."""
+    from paper_2510_03631_amd.serve import Server
+    banner("server with narrow variants in graphs")
+    dbs, queries, expected = env["dbs"], env["queries"], env["expected"]
+    chosen = {4: "narrow_128x32_k128_s6", 8: "narrow_256x32_k128_s4", 16: "narrow_256x64_k128_s4"}
+    try:
+        for db in dbs:
+            for b, name in chosen.items():
+                db.set_variant(b, name)
+        # One slot per database and bursts per database, so batches of
+        # several queries form (and reach the narrow tiles).
+        with Server(dbs, max_batch=16, slots_per_db=1, use_graphs=True) as srv:
+            outs = {}
+            for rep in range(2):
+                for d in range(len(SHAPES)):
+                    for i in range(24):
+                        outs[(rep, d, i)] = np.zeros(SHAPES[d][0], dtype=np.uint32)
+                        srv.submit(d, queries[d][i], outs[(rep, d, i)])
+                srv.drain()
+                _ = to_host_u32(dbs[1].answer(to_dev_u32(queries[1][0])))   # eager work between
+            st = srv.stats()
+    finally:
+        for db in dbs:
+            for b in chosen:
+                db.set_variant(b, 0)
+    for (rep, d, i), out in outs.items():
+        assert np.array_equal(out, expected[d][i]), (rep, d, i)
+    assert st["failed"] == 0 and st["batches"] < st["completed"]
