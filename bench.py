@@ -517,7 +517,7 @@ def main() -> int:
                          "or chorB / oopB / ftrB with B queries")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         return 2
 
