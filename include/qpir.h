@@ -316,6 +316,16 @@ const char* pir_variant_name(uint32_t batch, uint32_t variant);
  */
 pir_status pir_db_set_variant(pir_db_t* db, uint32_t batch, uint32_t variant);
 uint32_t pir_db_get_variant(const pir_db_t* db, uint32_t batch);
+/*
+ * OR'ed into `batch` (>= 1) of pir_db_set_variant and pir_db_get_variant,
+ * selects the table of the row-gathered products (pir_hint_update_rows, with
+ * n in that bucket) instead of the whole-database one.  Scattered rows cost
+ * address-translation latency, so the two favour different pipelines and
+ * are tuned apart; a gathered call with no choice of its own takes the
+ * built-in choice for gathered rows.  The single-query path has no gathered
+ * form: batch == PIR_VARIANT_ROWS is PIR_ERR_INVALID_ARG.
+ */
+#define PIR_VARIANT_ROWS 0x80000000u
 
 /*
  * Serving loop: continuous batching of queries over resident databases

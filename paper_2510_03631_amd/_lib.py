@@ -294,14 +294,17 @@ class Database:
               "pir_answer_batch_modp")
         return out
 
-    def set_variant(self, batch: int, variant) -> None:
-        """Pin a kernel variant (index or name) for ``batch``'s bucket."""
+    def set_variant(self, batch: int, variant, rows: bool = False) -> None:
+        """Pin a kernel variant (index or name) for ``batch``'s bucket; with
+        ``rows``, for the row-gathered products (``hint_update_rows``)."""
         if isinstance(variant, str):
             variant = variant_names(batch).index(variant)
-        check(lib().pir_db_set_variant(self.handle, batch, int(variant)), "pir_db_set_variant")
+        key = batch | (VARIANT_ROWS if rows else 0)
+        check(lib().pir_db_set_variant(self.handle, key, int(variant)), "pir_db_set_variant")
 
-    def get_variant(self, batch: int) -> int:
-        return int(lib().pir_db_get_variant(self.handle, batch))
+    def get_variant(self, batch: int, rows: bool = False) -> int:
+        key = batch | (VARIANT_ROWS if rows else 0)
+        return int(lib().pir_db_get_variant(self.handle, key))
 
     def setup_hint(self, A: torch.Tensor, out: torch.Tensor = None, stream=None, ws=None):
         """``H = D A mod 2^32`` for ``A`` of shape C x n (``pir_setup_hint``)."""
@@ -340,6 +343,10 @@ class Database:
                                          _stream_ptr(stream, self.device)),
               "pir_hint_update_rows")
         return H
+
+
+# Flag of pir_db_set_variant's batch argument: the row-gathered table.
+VARIANT_ROWS = 0x80000000
 
 
 def variant_names(batch: int) -> list:

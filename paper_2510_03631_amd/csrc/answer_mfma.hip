@@ -1112,6 +1112,16 @@ uint32_t default_variant(const pir_db_t* db, uint32_t B) {
     return B <= kFewDefault ? kVarFew : default_gemm(db, B);
 }
 
+// Gathered rows (the incremental hint): scattered row addresses add
+// address-translation latency, which the three-stage 128 x 256 ring hides
+// best.  Whole call, 1311 scattered rows of the 131072 x 131072 database,
+// n = 1024, on two machines: 1001-1019 us, against 1007-1294 us for the
+// two-stage 256 x 256 tile that is fastest over the whole database (that
+// one took 1146 us for the same rows sorted, 980 us for consecutive rows).
+uint32_t default_rows(const pir_db_t* db, uint32_t B) {
+    return ring_ok(db) && padded_batch(B) >= 64u ? kVarRing256 : default_gemm(db, B);
+}
+
 struct SplitPlan {
     uint32_t splits, kts;
 };
@@ -1245,7 +1255,8 @@ uint32_t mfma_variant_count() { return kNumVariants; }
 
 const char* mfma_variant_name(uint32_t v) { return v < kNumVariants ? kVariants[v].name : nullptr; }
 
-bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
+bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v, bool gathered) {
+    if (gathered && v != 0 && v < kNumVariants && kVariants[v].kind == kFew) return false;
     return variant_valid(db, B, v);
 }
 
@@ -1265,8 +1276,8 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
     if (!ws || ws_bytes < mfma_workspace_bytes(db, B) || ((uintptr_t)ws % kWsAlign))
         return PIR_ERR_WORKSPACE;
 
-    uint32_t v = db->variant[batch_bucket(B)];
-    if (v == 0 || !variant_valid(db, B, v)) v = default_variant(db, B);
+    uint32_t v = (rows ? db->variant_rows : db->variant)[batch_bucket(B)];
+    if (v == 0 || !variant_valid(db, B, v)) v = rows ? default_rows(db, B) : default_variant(db, B);
     if (rows && kVariants[v].kind == kFew) v = default_gemm(db, B);
     if (exact && kVariants[v].kind != kRing && kVariants[v].kind != kFew)
         v = (B <= kFewDefault || (B <= kFewMax && !ring_ok(db))) ? kVarFew : default_gemm(db, B);

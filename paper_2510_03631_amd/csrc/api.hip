@@ -199,20 +199,25 @@ const char* pir_variant_name(uint32_t batch, uint32_t variant) {
 
 pir_status pir_db_set_variant(pir_db_t* db, uint32_t batch, uint32_t variant) {
     if (!db_ok(db)) return PIR_ERR_INVALID_ARG;
+    const bool gathered = (batch & PIR_VARIANT_ROWS) != 0;
+    batch &= ~PIR_VARIANT_ROWS;
     if (batch > kMaxBatch) return PIR_ERR_SHAPE;
+    if (gathered && batch == 0) return PIR_ERR_INVALID_ARG;
     if (batch == 0) {
         if (variant >= gemv_variant_count()) return PIR_ERR_INVALID_ARG;
     } else {
         if (variant >= mfma_variant_count()) return PIR_ERR_INVALID_ARG;
-        if (!mfma_variant_valid(db, batch, variant)) return PIR_ERR_UNSUPPORTED;
+        if (!mfma_variant_valid(db, batch, variant, gathered)) return PIR_ERR_UNSUPPORTED;
     }
-    db->variant[batch_bucket(batch)] = (uint8_t)variant;
+    (gathered ? db->variant_rows : db->variant)[batch_bucket(batch)] = (uint8_t)variant;
     return PIR_OK;
 }
 
 uint32_t pir_db_get_variant(const pir_db_t* db, uint32_t batch) {
-    if (!db_ok(db) || batch > kMaxBatch) return 0;
-    return db->variant[batch_bucket(batch)];
+    const bool gathered = (batch & PIR_VARIANT_ROWS) != 0;
+    batch &= ~PIR_VARIANT_ROWS;
+    if (!db_ok(db) || batch > kMaxBatch || (gathered && batch == 0)) return 0;
+    return (gathered ? db->variant_rows : db->variant)[batch_bucket(batch)];
 }
 
 }  // extern "C"

@@ -19,7 +19,8 @@ struct pir_db {
     uint32_t* rowsum;      // device, rows words: sum_j D[r][j]
     int device;
     bool aligned;          // D and pitch are multiples of 16
-    uint8_t variant[kBuckets];   // kernel variant per batch bucket (0 = built-in choice)
+    uint8_t variant[kBuckets];        // kernel variant per batch bucket (0 = built-in choice)
+    uint8_t variant_rows[kBuckets];   // the same for row-gathered products
     // Cached split-K bound per padded-batch bucket: (N << 40) | (splits x rows),
     // 0 when not yet computed (see answer_mfma.hip).
     mutable std::atomic<uint64_t> split_rows[kBuckets];
@@ -83,7 +84,7 @@ pir_status launch_scatter_rows(const pir_db_t* db, const uint32_t* rows, uint32_
 pir_status mfma_init();
 uint32_t mfma_variant_count();
 const char* mfma_variant_name(uint32_t v);
-bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v);
+bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v, bool gathered);
 size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B);
 // modulus == 0: Out mod 2^32; otherwise Out mod modulus (field form).
 pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,

@@ -6,10 +6,13 @@ database shape and the batch size (the paper likewise picks its tile sizes
 from the query count and dimensions, Algorithm 4).  The tuner times each
 valid variant with HIP events on the device and records the fastest in a
 JSON table keyed by ``"RxC"`` and batch size; :func:`apply` installs a
-table entry on an open database with ``pir_db_set_variant``.
+table entry on an open database with ``pir_db_set_variant``.  Row-gathered
+products (the incremental hint after a refresh) are timed apart, on a
+random 1% of the rows, and recorded under ``"r<n>"``: scattered rows favour
+deeper pipelines than the whole database does.
 
     python -m paper_2510_03631_amd.tune --shape 32768x32768 --batches 0,64,1024 \
-        --out paper_2510_03631_amd/tiles.json
+        --rows-batches 1024 --out paper_2510_03631_amd/tiles.json
 """
 from __future__ import annotations
 
@@ -37,17 +40,29 @@ def _time_call(fn, reps: int) -> float:
     return start.elapsed_time(stop) / reps * 1e3   # microseconds
 
 
-def tune_database(db: Database, batches, reps: int = 5, log=print, modulus: int = 0) -> dict:
+def tune_database(db: Database, batches, reps: int = 5, log=print, modulus: int = 0,
+                  rows_frac: float = 0.0) -> dict:
     """Time every valid variant for each batch size; return {batch: {name: us}}.
 
     With ``modulus`` set, batched calls are timed in the field form
     (``answer_batch_modp``), which runs only the split-K capable variants.
+    With ``rows_frac`` set, each batch size ``n`` is timed as the incremental
+    hint over that fraction of the rows (``hint_update_rows``) and keyed
+    ``"r<n>"``.
     """
     import torch
     results = {}
     for B in batches:
         names = variant_names(B)
-        if B == 0:
+        gathered = rows_frac > 0 and B > 0
+        if gathered:
+            m = max(1, round(rows_frac * db.rows))
+            rows = torch.randperm(db.rows, device=db.device)[:m].to(torch.int32)
+            A = torch.randint(-2**31, 2**31 - 1, (db.cols, B), dtype=torch.int32, device=db.device)
+            H = torch.zeros((db.rows, B), dtype=torch.int32, device=db.device)
+            ws = db.workspace(B)
+            fn = lambda: db.hint_update_rows(rows, A, H, ws=ws)
+        elif B == 0:
             q = torch.randint(-2**31, 2**31 - 1, (db.cols,), dtype=torch.int32, device=db.device)
             out = torch.empty(db.rows, dtype=torch.int32, device=db.device)
             ws = db.workspace(0)
@@ -61,17 +76,18 @@ def tune_database(db: Database, batches, reps: int = 5, log=print, modulus: int 
             else:
                 fn = lambda: db.answer_batch(Q, out=out, ws=ws)
         times = {}
+        key = f"r{B}" if gathered else B
         for v, name in enumerate(names):
             if v == 0 or (modulus and B and not name.startswith(("ring", "narrow", "few"))):
                 continue
             try:
-                db.set_variant(B, v)
+                db.set_variant(B, v, rows=gathered)
             except PirError:
                 continue   # not valid for this database / batch
             times[name] = _time_call(fn, reps)
-            log(f"  {db.rows}x{db.cols} B={B:5d} {name:18s} {times[name]:10.1f} us")
-        db.set_variant(B, 0)
-        results[B] = times
+            log(f"  {db.rows}x{db.cols} B={key!s:>6} {name:18s} {times[name]:10.1f} us")
+        db.set_variant(B, 0, rows=gathered)
+        results[key] = times
     return results
 
 
@@ -93,8 +109,9 @@ def apply(db: Database, table: dict = None) -> int:
     entry = table.get(f"{db.rows}x{db.cols}", {})
     n = 0
     for B, name in entry.get("best", {}).items():
+        gathered = B.startswith("r")
         try:
-            db.set_variant(int(B), name)
+            db.set_variant(int(B[1:] if gathered else B), name, rows=gathered)
             n += 1
         except (PirError, ValueError):
             pass
@@ -109,17 +126,25 @@ def main(argv=None) -> int:
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--modulus", type=int, default=0,
                     help="time the field form mod this prime (Goldberg shapes)")
+    ap.add_argument("--rows-batches", default="",
+                    help="hint widths n to time as incremental hints (row-gathered)")
+    ap.add_argument("--rows-frac", type=float, default=0.01,
+                    help="fraction of the rows an incremental hint recomputes")
     args = ap.parse_args(argv)
     import torch
     import workload
     table = load(args.out)
-    batches = [int(b) for b in args.batches.split(",")]
+    batches = [int(b) for b in args.batches.split(",") if b]
+    rows_batches = [int(b) for b in args.rows_batches.split(",") if b]
     for shp in args.shape:
         R, C = (int(x) for x in shp.lower().split("x"))
         D = workload.device_db(R, C, workload.SEED_BASE + 77, "cuda")
         with Database(D) as db:
-            res = tune_database(db, batches, args.reps,
-                                log=lambda m: print(m, flush=True), modulus=args.modulus)
+            log = lambda m: print(m, flush=True)
+            res = tune_database(db, batches, args.reps, log=log, modulus=args.modulus)
+            if rows_batches:
+                res.update(tune_database(db, rows_batches, args.reps, log=log,
+                                         rows_frac=args.rows_frac))
         entry = table.setdefault(f"{R}x{C}", {"best": {}, "us": {}})
         entry["best"].update(best(res))          # merge: other batch sizes keep their choice
         entry["us"].update({str(B): t for B, t in res.items()})

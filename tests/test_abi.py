@@ -75,6 +75,17 @@ def test_argument_checks_before_any_device_call(qpir):
     assert lib.pir_chor_answer(None, 4, 4, 4, None, 0, None, None) == 0
 
 
+def test_gathered_variant_flag(qpir):
+    # The flag that selects the row-gathered variant table has the value the
+    # header defines, and the handle checks still come first.
+    from paper_2510_03631_amd._lib import VARIANT_ROWS
+    m = re.search(r"#define\s+PIR_VARIANT_ROWS\s+(0x[0-9a-fA-F]+)u", open(HEADER).read())
+    assert m and int(m.group(1), 16) == VARIANT_ROWS
+    lib = qpir.lib()
+    assert lib.pir_db_set_variant(None, VARIANT_ROWS | 64, 1) == 1
+    assert lib.pir_db_get_variant(None, VARIANT_ROWS | 64) == 0
+
+
 def test_variant_tables(qpir):
     qp = qpir
     names0 = qp.variant_names(0)

@@ -63,7 +63,7 @@ def test_incremental_hint_gathered_rows(qp, m, n):
         db.update_rows(rows_d, to_dev_u8(new))
         for v, name in _ring_variants(qp, n):
             try:
-                db.set_variant(n, v)
+                db.set_variant(n, v, rows=True)
             except qp.PirError:
                 continue
             banner(f"incremental hint m={m} n={n} {name}")

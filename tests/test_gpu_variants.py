@@ -71,6 +71,7 @@ def test_hint_update_variants(qp):
         with qp.Database(Dd) as db:
             try:
                 db.set_variant(n, v)
+                db.set_variant(n, v, rows=True)
             except qp.PirError:
                 continue
             banner(f"hint update variant {name}")
@@ -81,6 +82,30 @@ def test_hint_update_variants(qp):
             db.hint_update_rows(rd, Ad, H)
             torch.cuda.synchronize()
             assert np.array_equal(to_host_u32(H), exp), name
+
+
+def test_gathered_variant_table(qp):
+    # Row-gathered products keep their own variant table: pinning one table
+    # leaves the other alone, the single-query path has no gathered form,
+    # and the dot4 'few' kernel (whole database only) is refused for it.
+    import torch
+    banner("gathered variant table")
+    D = torch.zeros((256, 1024), dtype=torch.uint8, device="cuda")
+    with qp.Database(D) as db:
+        names = qp.variant_names(64)
+        db.set_variant(64, "ring_128x128_k128_s4")
+        db.set_variant(64, "ring8w_256x256_s4", rows=True)
+        assert names[db.get_variant(64)] == "ring_128x128_k128_s4"
+        assert names[db.get_variant(64, rows=True)] == "ring8w_256x256_s4"
+        db.set_variant(64, 0, rows=True)
+        assert db.get_variant(64, rows=True) == 0
+        assert names[db.get_variant(64)] == "ring_128x128_k128_s4"
+        with pytest.raises(qp.PirError):
+            db.set_variant(0, 1, rows=True)
+        with pytest.raises(qp.PirError):
+            db.set_variant(2, "few", rows=True)
+        db.set_variant(2, "few")
+        assert db.get_variant(2, rows=True) == 0
 
 
 def test_unaligned_database_rejects_ring_variants(qp):
