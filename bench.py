@@ -295,15 +295,24 @@ def serving_run(srv, t_off, which, qs) -> dict:
     import numpy as np
     s0 = srv.stats()
     t0 = time.perf_counter()
-    first = srv.replay((t_off * 1e9).astype(np.uint64), which, qs)
+    off_ns = (t_off * 1e9).astype(np.uint64)
+    first = srv.replay(off_ns, which, qs)
     srv.drain()
     wall = time.perf_counter() - t0
     s1 = srv.stats()
     n = s1["completed"] - s0["completed"]
-    lat = srv.latencies(first, n).astype(np.float64) / 1e6
+    lat_ns = srv.latencies(first, n)
+    lat = lat_ns.astype(np.float64) / 1e6
     batches = s1["batches"] - s0["batches"]
+    if n == len(off_ns) and n:
+        # Span from the replay's start to the last answer (scheduled arrival
+        # plus latency), which leaves out the host-side marshalling of the
+        # trace before the replay starts.
+        span = float((off_ns + lat_ns).max()) / 1e9
+    else:
+        span = wall
     return {"offered_qps": round(len(t_off) / float(t_off[-1]), 1) if len(t_off) else 0.0,
-            "achieved_qps": round(n / wall, 1), "queries": int(n),
+            "achieved_qps": round(n / span, 1), "queries": int(n),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "max_ms": round(float(lat.max()), 3),
@@ -343,26 +352,36 @@ def serving_bench(args) -> dict:
         pick = gg.integers(0, 16, size=len(t))
         return t, which, [pool[d][i] for d, i in zip(which, pick)]
 
+    budget = 2 << 30
+    inflight = 4
+    p99_bound = 10.0
     out = {"databases": [f"{R}x{C}" for R, C in workload.SERVING_DBS],
            "db_bytes": int(sum(R * C for R, C in workload.SERVING_DBS)),
-           "budget_bytes": 2 << 30}
-    budget = 2 << 30
-    with Server(dbs, max_batch=64, slots_per_db=2, mem_budget_bytes=budget) as srv:
+           "budget_bytes": budget, "max_batch": 64, "slots_per_db": 2,
+           "max_inflight": inflight, "p99_bound_ms": p99_bound}
+
+    def sweep(srv, rates, seed_off):
+        runs = []
+        for rate in rates:
+            t, w, qs = trace(rate, 2.0, int(rate) + seed_off)
+            runs.append(serving_run(srv, t, w, qs))
+            if runs[-1]["p99_ms"] > p99_bound:
+                break   # past saturation: higher rates only queue longer
+        ok = [r["achieved_qps"] for r in runs if r["p99_ms"] <= p99_bound]
+        return runs, (max(ok) if ok else 0.0)
+
+    with Server(dbs, max_batch=64, slots_per_db=2, mem_budget_bytes=budget,
+                max_inflight=inflight) as srv:
         t, w, qs = trace(workload.SERVING_RATE, 1.0, 1)
         serving_run(srv, t, w, qs)                       # warm-up
         t, w, qs = trace(workload.SERVING_RATE, args.serving_seconds, 2)
         out["at_2000qps"] = serving_run(srv, t, w, qs)
-        sweep = []
-        for rate in (8000.0, 20000.0, 40000.0):
-            t, w, qs = trace(rate, 2.0, int(rate))
-            sweep.append(serving_run(srv, t, w, qs))
-        out["batched_sweep"] = sweep
-    with Server(dbs, max_batch=1, slots_per_db=2, mem_budget_bytes=budget) as srv:
-        plain = []
-        for rate in (2000.0, 8000.0, 20000.0):
-            t, w, qs = trace(rate, 2.0, int(rate) + 1)
-            plain.append(serving_run(srv, t, w, qs))
-        out["plain_sweep"] = plain
+        out["batched_sweep"], out["batched_max_qps_at_p99_bound"] = sweep(
+            srv, (8000.0, 20000.0, 40000.0, 80000.0, 160000.0, 240000.0, 320000.0), 0)
+    with Server(dbs, max_batch=1, slots_per_db=2, mem_budget_bytes=budget,
+                max_inflight=inflight) as srv:
+        out["plain_sweep"], out["plain_max_qps_at_p99_bound"] = sweep(
+            srv, (2000.0, 8000.0, 16000.0, 20000.0), 1)
     for db in dbs:
         db.close()
     return out

@@ -37,7 +37,7 @@ _ST = ctypes.c_int
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_uint32), ("slots_per_db", ctypes.c_uint32),
                 ("mem_budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_uint32),
-                ("use_graphs", ctypes.c_uint32)]
+                ("use_graphs", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):

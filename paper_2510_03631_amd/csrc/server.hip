@@ -111,7 +111,6 @@ struct pir_server {
     pir_status fault = PIR_OK;
     uint64_t used = 0, peak = 0;
     uint64_t n_batches = 0, n_batched = 0, n_done = 0, n_failed = 0, n_rejected = 0;
-    uint32_t rr = 0;                    // round-robin start over databases
 
     uint64_t batch_cost(const DbQueue& d, uint32_t size) const {
         const size_t ws = size == 1 ? pir_workspace_bytes(d.db, 0) : pir_workspace_bytes(d.db, size);
@@ -196,64 +195,81 @@ struct pir_server {
         s.batch.clear();
     }
 
+    // Free slot of a database, or null.
+    static Slot* free_slot(DbQueue& d) {
+        for (auto& x : d.slots)
+            if (!x.busy) return &x;
+        return nullptr;
+    }
+
     void scheduler_loop() {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
+        std::vector<char> blocked;
         for (;;) {
             bool launched = false;
             const size_t nd = dbs.size();
-            for (size_t step = 0; step < nd && fault == PIR_OK; ++step) {
-                DbQueue& d = dbs[(rr + step) % nd];
-                while (!d.queue.empty() && !d.paused) {
-                    Slot* s = nullptr;
-                    for (auto& x : d.slots)
-                        if (!x.busy) { s = &x; break; }
-                    if (!s) break;
-                    uint32_t n = (uint32_t)std::min<size_t>(d.queue.size(), cfg.max_batch);
-                    uint32_t size = pow2_ceil(n);
-                    while (size > 1 && used + batch_cost(d, size) > cfg.mem_budget_bytes) size >>= 1;
-                    if (used + batch_cost(d, size) > cfg.mem_budget_bytes) break;   // wait
-                    n = std::min(n, size);
-                    s->batch.assign(d.queue.begin(), d.queue.begin() + n);
-                    d.queue.erase(d.queue.begin(), d.queue.begin() + n);
-                    s->busy = true;
-                    s->size = size;
-                    s->cost = batch_cost(d, size);
-                    used += s->cost;
-                    peak = std::max(peak, used);
-                    ++d.inflight;
-                    ++n_batches;
-                    n_batched += n;
-                    for (Req* r : s->batch) r->state.store(kRunning, std::memory_order_relaxed);
-                    lk.unlock();
-                    // Pack the queries (query-major rows of C words) and launch.
-                    for (uint32_t b = 0; b < n; ++b)
-                        memcpy(s->h_Q + (size_t)b * d.C, s->batch[b]->h_q, d.C * 4);
-                    pir_status st = PIR_OK;
-                    if (cfg.use_graphs) {
-                        if (hipGraphLaunch(s->exec[log2_floor(size)], s->stream) != hipSuccess)
-                            st = PIR_ERR_DEVICE;
-                    } else {
-                        st = enqueue(d, *s, size);
-                    }
-                    if (st == PIR_OK && hipEventRecord(s->done, s->stream) != hipSuccess)
-                        st = PIR_ERR_DEVICE;
-                    lk.lock();
-                    if (st != PIR_OK) {
-                        fault = st;
-                        fail_batch(*s);
-                        s->busy = false;
-                        used -= s->cost;
-                        --d.inflight;
-                        cv_done.notify_all();
-                        break;
-                    }
-                    inflight.push_back(s);
-                    launched = true;
-                    cv_done.notify_all();
+            blocked.assign(nd, 0);
+            // Launch while the device takes more batches: each time, the
+            // database whose oldest request has waited longest, with
+            // everything it has queued (up to max_batch and the budget).
+            while (fault == PIR_OK && (cfg.max_inflight == 0 || inflight.size() < cfg.max_inflight)) {
+                size_t pick = nd;
+                for (size_t i = 0; i < nd; ++i) {
+                    DbQueue& c = dbs[i];
+                    if (c.queue.empty() || c.paused || blocked[i] || !free_slot(c)) continue;
+                    if (pick == nd || c.queue.front()->t_arrival < dbs[pick].queue.front()->t_arrival)
+                        pick = i;
                 }
+                if (pick == nd) break;
+                DbQueue& d = dbs[pick];
+                Slot* s = free_slot(d);
+                uint32_t n = (uint32_t)std::min<size_t>(d.queue.size(), cfg.max_batch);
+                uint32_t size = pow2_ceil(n);
+                while (size > 1 && used + batch_cost(d, size) > cfg.mem_budget_bytes) size >>= 1;
+                if (used + batch_cost(d, size) > cfg.mem_budget_bytes) {   // wait for memory
+                    blocked[pick] = 1;
+                    continue;
+                }
+                n = std::min(n, size);
+                s->batch.assign(d.queue.begin(), d.queue.begin() + n);
+                d.queue.erase(d.queue.begin(), d.queue.begin() + n);
+                s->busy = true;
+                s->size = size;
+                s->cost = batch_cost(d, size);
+                used += s->cost;
+                peak = std::max(peak, used);
+                ++d.inflight;
+                ++n_batches;
+                n_batched += n;
+                for (Req* r : s->batch) r->state.store(kRunning, std::memory_order_relaxed);
+                lk.unlock();
+                // Pack the queries (query-major rows of C words) and launch.
+                for (uint32_t b = 0; b < n; ++b)
+                    memcpy(s->h_Q + (size_t)b * d.C, s->batch[b]->h_q, d.C * 4);
+                pir_status st = PIR_OK;
+                if (cfg.use_graphs) {
+                    if (hipGraphLaunch(s->exec[log2_floor(size)], s->stream) != hipSuccess)
+                        st = PIR_ERR_DEVICE;
+                } else {
+                    st = enqueue(d, *s, size);
+                }
+                if (st == PIR_OK && hipEventRecord(s->done, s->stream) != hipSuccess)
+                    st = PIR_ERR_DEVICE;
+                lk.lock();
+                if (st != PIR_OK) {
+                    fault = st;
+                    fail_batch(*s);
+                    s->busy = false;
+                    used -= s->cost;
+                    --d.inflight;
+                    cv_done.notify_all();
+                    break;
+                }
+                inflight.push_back(s);
+                launched = true;
+                cv_done.notify_all();
             }
-            rr = nd ? (rr + 1) % (uint32_t)nd : 0;
             if (fault != PIR_OK) {   // fail whatever is queued
                 for (auto& d : dbs) {
                     for (Req* r : d.queue) {

@@ -26,14 +26,21 @@ def _host_words(a: np.ndarray, n: int, name: str) -> np.ndarray:
 
 
 class Server:
-    """Continuous-batching PIR server over open :class:`Database` objects."""
+    """Continuous-batching PIR server over open :class:`Database` objects.
+
+    ``max_inflight`` caps the batches on the device over all databases
+    (0: only ``slots_per_db`` bounds them).  Under load the cap keeps
+    requests queued while the device is busy, so they leave in larger
+    batches; the database with the longest-waiting request goes first.
+    """
 
     def __init__(self, dbs, max_batch: int = 64, slots_per_db: int = 2,
-                 mem_budget_bytes: int = 2 << 30, max_queue: int = 0, use_graphs: bool = True):
+                 mem_budget_bytes: int = 2 << 30, max_queue: int = 0, use_graphs: bool = True,
+                 max_inflight: int = 4):
         self.dbs = list(dbs)
         cfg = ServerConfig(max_batch=max_batch, slots_per_db=slots_per_db,
                            mem_budget_bytes=mem_budget_bytes, max_queue=max_queue,
-                           use_graphs=1 if use_graphs else 0)
+                           use_graphs=1 if use_graphs else 0, max_inflight=max_inflight)
         h = _P()
         import torch
         self.device = self.dbs[0].device

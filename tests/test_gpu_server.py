@@ -79,6 +79,28 @@ def test_burst_forms_batches(env):
     assert st["batches"] < 24          # arrivals during a running batch were batched
 
 
+@pytest.mark.parametrize("max_inflight", [1, 0])
+def test_inflight_cap(env, max_inflight):
+    # One batch on the device at a time (everything else waits in the
+    # queues, oldest database first), or no cap beyond the slots: the answers
+    # are the same either way.
+    from paper_2510_03631_amd.serve import Server
+    banner(f"server max_inflight={max_inflight}")
+    dbs, queries, expected = env["dbs"], env["queries"], env["expected"]
+    with Server(dbs, max_batch=16, slots_per_db=2, max_inflight=max_inflight) as srv:
+        outs = {}
+        for d, i in _mixed_order(env, 11):
+            outs[(d, i)] = np.zeros(SHAPES[d][0], dtype=np.uint32)
+            srv.submit(d, queries[d][i], outs[(d, i)])
+        srv.drain()
+        st = srv.stats()
+    for (d, i), out in outs.items():
+        assert np.array_equal(out, expected[d][i]), (d, i)
+    assert st["completed"] == 24 * len(SHAPES) and st["failed"] == 0
+    if max_inflight == 1:
+        assert st["batches"] < st["completed"]   # queued work left in batches
+
+
 def test_memory_budget_admission(env):
     from paper_2510_03631_amd.serve import Server
     banner("server tiny memory budget")
