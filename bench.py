@@ -377,7 +377,7 @@ def serving_bench(args) -> dict:
         t, w, qs = trace(workload.SERVING_RATE, args.serving_seconds, 2)
         out["at_2000qps"] = serving_run(srv, t, w, qs)
         out["batched_sweep"], out["batched_max_qps_at_p99_bound"] = sweep(
-            srv, (8000.0, 20000.0, 40000.0, 80000.0, 160000.0, 240000.0, 320000.0), 0)
+            srv, (8000.0, 20000.0, 40000.0, 80000.0, 160000.0, 240000.0, 280000.0, 320000.0), 0)
     with Server(dbs, max_batch=1, slots_per_db=2, mem_budget_bytes=budget,
                 max_inflight=inflight) as srv:
         out["plain_sweep"], out["plain_max_qps_at_p99_bound"] = sweep(
