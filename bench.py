@@ -5,7 +5,9 @@ Headline: single-query Answer GB/s of database scanned on a 32768 x 32768
 uint8 database (1 GiB) with one LWE query (n = 1024, sigma = 6.4).  A step is
 one Answer over the resident database; inputs are in HBM before timing.
 
-Also reported on the same line: the 64-query batched Answer and the offline
+Also reported on the same line: the spread of single launches (median, min,
+p90) and the same Answer with the query copied in from pinned host memory
+(and the answer copied back); the 64-query batched Answer and the offline
 hint on the same database (matrix cores); a 16 GiB database (256-query batch,
 hint, 1% refresh with incremental hint); Chor XOR PIR, the Goldberg field
 form and the CIP-PIR offline/online split at 2^18 records of 3 KB; the
@@ -72,6 +74,30 @@ def time_on_stream(fn, steps: int, stream):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall, start.elapsed_time(stop) / 1e3
+
+
+def per_launch_us(fn, reps: int, stream):
+    """Run fn() `reps` times, each between its own pair of events on
+    `stream`; return the per-call device times in microseconds."""
+    import numpy as np
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) * 1e3 for a, b in evs])
+
+
+def spread(us, nbytes: int) -> dict:
+    import numpy as np
+    med = float(np.median(us))
+    return {"reps": int(len(us)), "median_us": round(med, 2), "min_us": round(float(us.min()), 2),
+            "p90_us": round(float(np.percentile(us, 90)), 2),
+            "median_gbs_db": round(nbytes / (med * 1e-6) / 1e9, 1)}
 
 
 def cpu_baseline(R: int, C: int, seconds: float = 10.0):
@@ -166,6 +192,49 @@ def large_bench(stream) -> dict:
         "hint_fraction_recomputed": round(m / R, 4),
     }
     del D, Q, out, A, H, new, wsb, wsh
+    torch.cuda.empty_cache()
+    return res
+
+
+def client_bench(stream) -> dict:
+    """LWE client steps on the device at the spectrum shape (C = R = 32768,
+    n = 1024): query generation Qt = A S + E + 2^24 u_col and decode
+    ((a - H s + 2^23) mod 2^32) >> 24, for 1, 4, 16 and 64 queries.  Bytes are
+    the algorithmic ones: the matrix once, plus the per-query vectors."""
+    import torch
+    import paper_2510_03631_amd as qp
+    import workload
+    dev = torch.device("cuda:0")
+    C = R = 32768
+    n = workload.LWE_N
+    A = workload.device_u32((C, n), workload.SEED_BASE + 60, dev)
+    H = workload.device_u32((R, n), workload.SEED_BASE + 61, dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(workload.SEED_BASE + 62)
+    res = {"workload": f"A {C} x {n} and H {R} x {n} uint32 words (128 MiB each)"}
+    for B in (1, 4, 16, 64):
+        S = workload.device_u32((B, n), workload.SEED_BASE + 63 + B, dev)
+        E = torch.randint(-40, 41, (B, C), dtype=torch.int32, device=dev, generator=gen)
+        cols = torch.randint(0, C, (B,), dtype=torch.int32, device=dev, generator=gen)
+        Qt = torch.empty((B, C), dtype=torch.int32, device=dev)
+        ans = workload.device_u32((B, R), workload.SEED_BASE + 64 + B, dev)
+        m = torch.empty((B, R), dtype=torch.uint8, device=dev)
+        fq = lambda: qp.client_query(A, S, E, cols, out=Qt)
+        fd = lambda: qp.client_decode(H, S, ans, out=m)
+        fq()
+        fd()
+        _, tq = time_on_stream(fq, 10, stream)
+        _, td = time_on_stream(fd, 10, stream)
+        tq /= 10
+        td /= 10
+        bq = 4 * C * n + B * (4 * n + 8 * C)
+        bd = 4 * R * n + B * (4 * n + 5 * R)
+        res[f"B{B}"] = {"query_us": round(tq * 1e6, 1), "query_gbs": round(bq / tq / 1e9, 1),
+                        "query_hbm_frac": round(bq / tq / 1e9 / HBM_PEAK_GBS, 4),
+                        "decode_us": round(td * 1e6, 1), "decode_gbs": round(bd / td / 1e9, 1),
+                        "decode_hbm_frac": round(bd / td / 1e9 / HBM_PEAK_GBS, 4),
+                        "macs_per_s": round(C * n * B / tq, 1)}
+    del A, H
     torch.cuda.empty_cache()
     return res
 
@@ -412,6 +481,26 @@ def profile_mode(args, dev, stream) -> int:
                           "copy_us": round(t * 1e6, 2),
                           "copy_gbs_read_plus_write": round(2 * x.numel() * 4 / t / 1e9, 1)}))
         return 0
+    if args.profile.startswith("client"):
+        # clientB: query generation then decode for B queries at C = R = 32768.
+        B = int(args.profile[len("client"):])
+        A = workload.device_u32((C, n), workload.SEED_BASE + 60, dev)
+        H = workload.device_u32((R, n), workload.SEED_BASE + 61, dev)
+        S = workload.device_u32((B, n), workload.SEED_BASE + 63 + B, dev)
+        E = torch.zeros((B, C), dtype=torch.int32, device=dev)
+        cols = torch.zeros((B,), dtype=torch.int32, device=dev)
+        Qt = torch.empty((B, C), dtype=torch.int32, device=dev)
+        m = torch.empty((B, R), dtype=torch.uint8, device=dev)
+
+        def fn():
+            qp.client_query(A, S, E, cols, out=Qt)
+            qp.client_decode(H, S, Qt, out=m)
+        for _ in range(args.warmup):
+            fn()
+        wall, ev = time_on_stream(fn, args.steps, stream)
+        print(json.dumps({"profile": args.profile, "steps": args.steps,
+                          "avg_us_query_plus_decode": round(ev / args.steps * 1e6, 2)}))
+        return 0
     if args.profile.startswith(("chor", "oop", "ftr")):
         return profile_instantiation(args, dev, stream)
     if args.profile == "intmm":
@@ -529,11 +618,12 @@ def main() -> int:
     ap.add_argument("--no-chor", action="store_true")
     ap.add_argument("--no-ftr", action="store_true")
     ap.add_argument("--no-oop", action="store_true")
+    ap.add_argument("--no-client", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--profile",
                     help="run only one kernel family (for rocprofv3 runs) and exit: answer, "
                          "batchB, hint, update (incremental hint, 16 GiB), calibrate, intmm, "
-                         "or chorB / oopB / ftrB with B queries")
+                         "or chorB / oopB / ftrB / clientB with B queries")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
@@ -606,6 +696,28 @@ def main() -> int:
                      "avg_launch_us": round(kern_s * 1e6, 2)},
     }
 
+    # Spread of single launches, then the same launch with the query copied
+    # in from pinned host memory first, and with the answer copied back.
+    log("single-query spread and host round trip")
+    result["single_query_spread"] = spread(per_launch_us(step, 50, stream), bytes_db)
+    q_host = torch.empty(C, dtype=torch.int32, pin_memory=True)
+    q_host.copy_(q.cpu())
+    a_host = torch.empty(R, dtype=torch.int32, pin_memory=True)
+    q_in = torch.empty_like(q)
+
+    def with_h2d():
+        q_in.copy_(q_host, non_blocking=True)
+        db.answer(q_in, out=a, ws=ws)
+
+    def round_trip():
+        with_h2d()
+        a_host.copy_(a, non_blocking=True)
+
+    result["single_query_host"] = {
+        "h2d_q_then_answer": spread(per_launch_us(with_h2d, 50, stream), bytes_db),
+        "h2d_q_answer_d2h_a": spread(per_launch_us(round_trip, 50, stream), bytes_db),
+        "note": "pinned host buffers of 128 KiB each way; value above excludes them"}
+
     if not args.no_batch:
         B = 64
         log("batched answer, 64 queries")
@@ -665,6 +777,10 @@ def main() -> int:
             db.close()
         torch.cuda.empty_cache()
         result["oop"] = oop_bench(stream)
+
+    if not args.no_client:
+        log("LWE client steps: query generation and decode, 1 / 4 / 16 / 64 queries")
+        result["client"] = client_bench(stream)
 
     if not args.no_serving:
         log("serving: 8 resident databases, Poisson arrivals, Zipf(1.1)")

@@ -22,7 +22,8 @@ def _dev_i32(a):
 
 
 @pytest.mark.parametrize("R,C,n,B", [(1024, 1024, 1024, 3), (333, 1000, 77, 17),
-                                     (64, 2048, 1500, 1), (2000, 300, 64, 40)])
+                                     (64, 2048, 1500, 1), (2000, 300, 64, 40),
+                                     (100, 512, 1030, 5), (1001, 1023, 256, 9)])
 def test_client_query_decode_round_trip(qp, R, C, n, B):
     banner(f"client round trip R={R} C={C} n={n} B={B}")
     g = workload.rng(R + C + n + B)
@@ -43,6 +44,25 @@ def test_client_query_decode_round_trip(qp, R, C, n, B):
     for b in range(B):
         assert np.array_equal(m[b], oracle.lwe_decode(ans_h[b], H_h, dr.s[b])), b
         assert np.array_equal(m[b], D[:, int(dr.col[b])]), b
+
+
+def test_client_unaligned_matrix(qp):
+    """A public matrix that starts 4 bytes into its allocation takes the
+    word-load path (n % 4 == 0 but not 16-byte aligned); same results."""
+    import torch
+    banner("client query, unaligned matrix")
+    g = workload.rng(31337)
+    C, n, B = 700, 512, 3
+    A = workload.uniform_u32(g, (C, n))
+    dr = workload.lwe_draws(g, C, n, B)
+    store = torch.zeros(C * n + 1, dtype=torch.int32, device="cuda")
+    store[1:] = to_dev_u32(A).view(-1)
+    Ad = store[1:].view(C, n)
+    assert Ad.data_ptr() % 16 != 0
+    Qt = to_host_u32(qp.client_query(Ad, to_dev_u32(dr.s), _dev_i32(dr.e),
+                                     to_dev_u32(dr.col.astype(np.uint32))))
+    for b in range(B):
+        assert np.array_equal(Qt[b], oracle.lwe_query(A, dr.s[b], dr.e[b], int(dr.col[b]))), b
 
 
 def test_client_decode_boundaries(qp):
