@@ -426,7 +426,7 @@ def serving_bench(args) -> dict:
     p99_bound = 10.0
     out = {"databases": [f"{R}x{C}" for R, C in workload.SERVING_DBS],
            "db_bytes": int(sum(R * C for R, C in workload.SERVING_DBS)),
-           "budget_bytes": budget, "max_batch": 64, "slots_per_db": 2,
+           "budget_bytes": budget, "max_batch": 64, "slots_per_db": 3,
            "max_inflight": inflight, "p99_bound_ms": p99_bound}
 
     def sweep(srv, rates, seed_off):
@@ -439,15 +439,16 @@ def serving_bench(args) -> dict:
         ok = [r["achieved_qps"] for r in runs if r["p99_ms"] <= p99_bound]
         return runs, (max(ok) if ok else 0.0)
 
-    with Server(dbs, max_batch=64, slots_per_db=2, mem_budget_bytes=budget,
+    with Server(dbs, max_batch=64, slots_per_db=3, mem_budget_bytes=budget,
                 max_inflight=inflight) as srv:
         t, w, qs = trace(workload.SERVING_RATE, 1.0, 1)
         serving_run(srv, t, w, qs)                       # warm-up
         t, w, qs = trace(workload.SERVING_RATE, args.serving_seconds, 2)
         out["at_2000qps"] = serving_run(srv, t, w, qs)
         out["batched_sweep"], out["batched_max_qps_at_p99_bound"] = sweep(
-            srv, (8000.0, 20000.0, 40000.0, 80000.0, 160000.0, 240000.0, 280000.0, 320000.0), 0)
-    with Server(dbs, max_batch=1, slots_per_db=2, mem_budget_bytes=budget,
+            srv, (8000.0, 20000.0, 40000.0, 80000.0, 160000.0, 240000.0, 320000.0, 360000.0,
+                  400000.0, 440000.0, 480000.0), 0)
+    with Server(dbs, max_batch=1, slots_per_db=3, mem_budget_bytes=budget,
                 max_inflight=inflight) as srv:
         out["plain_sweep"], out["plain_max_qps_at_p99_bound"] = sweep(
             srv, (2000.0, 8000.0, 16000.0, 20000.0), 1)

@@ -332,10 +332,11 @@ uint32_t pir_db_get_variant(const pir_db_t* db, uint32_t batch);
  * (the batched, latency-oriented response of Section 5.2).  Host-side
  * queues feed per-database slots (stream, pinned staging, device buffers);
  * a scheduler thread launches whatever has queued whenever a slot is free
- * (and fewer than max_inflight batches are on the device), the database
+ * (and fewer than max_inflight batches have kernels pending), the database
  * with the longest-waiting request first, as one HIP-graph replay per batch
- * (sizes rounded up to powers of two), and admits a batch only if its
- * device bytes fit the memory budget next to the batches already in flight.
+ * (sizes rounded up to powers of two) followed by the copy-out of its
+ * answers, and admits a batch only if its device bytes fit the memory
+ * budget next to the batches already in flight.
  * Latency runs from the request's (scheduled) arrival time to its answer
  * being in the caller's host buffer.
  */
@@ -349,10 +350,11 @@ typedef struct pir_server_config {
     uint32_t max_queue;         /* queued requests per database before submit
                                    returns PIR_ERR_BUSY; 0 = unbounded */
     uint32_t use_graphs;        /* 1: replay captured HIP graphs; 0: direct launches */
-    uint32_t max_inflight;      /* batches on the device over all databases; 0 = only
-                                   the slots bound it.  A cap keeps requests queued
-                                   while the device is busy, so they leave in larger
-                                   batches under load */
+    uint32_t max_inflight;      /* batches with kernels pending, over all databases
+                                   (one copying its answers out no longer counts);
+                                   0 = only the slots bound them.  A cap keeps requests
+                                   queued while the device is busy, so they leave in
+                                   larger batches under load */
 } pir_server_config;
 
 typedef struct pir_server_stats {

@@ -17,10 +17,14 @@
 //   leaves after the batches already in flight; otherwise it waits, and a
 //   smaller batch is formed when that fits;
 // * batch sizes are rounded up to powers of two; for every (slot, size) the
-//   copy-in, kernels and copy-out were captured once into a HIP graph at
-//   start, so a launch is one graph replay (padded queries are ignored);
+//   copy-in and kernels were captured once into a HIP graph at start, so a
+//   launch is one graph replay (padded queries are ignored), then an event
+//   marking the kernels done and the copy-out of the answers;
 // * batches for different databases run on different streams and overlap
-//   on the device;
+//   on the device; with max_inflight set, at most that many batches have
+//   kernels pending (a batch that only copies its answers out does not
+//   count), and each launch goes to the database whose oldest request has
+//   waited longest;
 // * a poller thread completes batches in any order, copies each answer to
 //   its caller's buffer and records the latency from the scheduled arrival
 //   time (open-loop: queueing delay is included).
@@ -60,6 +64,8 @@ struct Req {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    uint32_t* h_flag = nullptr;   // pinned word: 1 once the batch's kernels have run
+    uint32_t* d_flag = nullptr;   // the same word as the device addresses it
     uint32_t* h_Q = nullptr;   // pinned, max_batch x C (query-major)
     uint32_t* h_O = nullptr;   // pinned, max_batch x R (answer-major)
     uint32_t* d_Q = nullptr;
@@ -73,6 +79,7 @@ struct Slot {
     uint64_t cost = 0;         // budget bytes held while in flight
     uint32_t db = 0;           // owning database index
     bool busy = false;
+    bool computing = false;    // launched, kernels not yet finished
 };
 
 struct DbQueue {
@@ -83,6 +90,12 @@ struct DbQueue {
     bool paused = false;
     uint32_t inflight = 0;
 };
+
+// One word to host memory, visible to the host once the kernels before it
+// on the stream have finished.
+__global__ void k_raise_flag(uint32_t* flag) {
+    if (threadIdx.x == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 uint32_t log2_floor(uint32_t x) {
     uint32_t k = 0;
@@ -111,25 +124,58 @@ struct pir_server {
     pir_status fault = PIR_OK;
     uint64_t used = 0, peak = 0;
     uint64_t n_batches = 0, n_batched = 0, n_done = 0, n_failed = 0, n_rejected = 0;
+    uint32_t n_computing = 0;           // batches whose kernels have not finished
 
     uint64_t batch_cost(const DbQueue& d, uint32_t size) const {
         const size_t ws = size == 1 ? pir_workspace_bytes(d.db, 0) : pir_workspace_bytes(d.db, size);
         return (uint64_t)size * (d.R + d.C) * 4u + ws;
     }
 
-    pir_status enqueue(DbQueue& d, Slot& s, uint32_t size) {
+    // Batches of at least kDirectCopies queries move their queries in and
+    // answers out with plain stream copies around the graph of kernels
+    // (the DMA engines then overlap them with other batches' kernels);
+    // smaller ones keep both copies inside the graph, one launch in all.
+    static constexpr uint32_t kDirectCopies = 8;
+
+    pir_status copy_in(DbQueue& d, Slot& s, uint32_t size) {
+        return hipMemcpyAsync(s.d_Q, s.h_Q, (size_t)size * d.C * 4, hipMemcpyHostToDevice,
+                              s.stream) == hipSuccess ? PIR_OK : PIR_ERR_DEVICE;
+    }
+
+    pir_status copy_out(DbQueue& d, Slot& s, uint32_t size) {
+        return hipMemcpyAsync(s.h_O, s.d_O, (size_t)size * d.R * 4, hipMemcpyDeviceToHost,
+                              s.stream) == hipSuccess ? PIR_OK : PIR_ERR_DEVICE;
+    }
+
+    // The work captured per (slot, size); with `copies`, the two copies too.
+    pir_status enqueue(DbQueue& d, Slot& s, uint32_t size, bool copies) {
         hipStream_t st = s.stream;
-        if (hipMemcpyAsync(s.d_Q, s.h_Q, (size_t)size * d.C * 4, hipMemcpyHostToDevice, st) !=
-            hipSuccess)
-            return PIR_ERR_DEVICE;
-        pir_status r = size == 1
-                           ? pir_answer(d.db, s.d_Q, s.d_O, s.d_ws, s.ws_bytes, st)
-                           : pir_answer_batch_qmajor(d.db, s.d_Q, size, s.d_O, s.d_ws, s.ws_bytes, st);
+        pir_status r = copies ? copy_in(d, s, size) : PIR_OK;
         if (r != PIR_OK) return r;
-        if (hipMemcpyAsync(s.h_O, s.d_O, (size_t)size * d.R * 4, hipMemcpyDeviceToHost, st) !=
-            hipSuccess)
-            return PIR_ERR_DEVICE;
-        return PIR_OK;
+        r = size == 1 ? pir_answer(d.db, s.d_Q, s.d_O, s.d_ws, s.ws_bytes, st)
+                      : pir_answer_batch_qmajor(d.db, s.d_Q, size, s.d_O, s.d_ws, s.ws_bytes, st);
+        if (r != PIR_OK) return r;
+        // Kernels done: raise the slot's host flag, so the scheduler stops
+        // counting the batch against max_inflight.
+        k_raise_flag<<<1, 64, 0, st>>>(s.d_flag);
+        if (hipGetLastError() != hipSuccess) return PIR_ERR_DEVICE;
+        return copies ? copy_out(d, s, size) : PIR_OK;
+    }
+
+    // One batch: its copies and kernels (a graph replay or direct launches),
+    // then the event the poller waits for.
+    pir_status launch(DbQueue& d, Slot& s, uint32_t size) {
+        const bool direct = size >= kDirectCopies;
+        pir_status r = PIR_OK;
+        if (cfg.use_graphs) {
+            if (direct && (r = copy_in(d, s, size)) != PIR_OK) return r;
+            if (hipGraphLaunch(s.exec[log2_floor(size)], s.stream) != hipSuccess)
+                return PIR_ERR_DEVICE;
+            if (direct && (r = copy_out(d, s, size)) != PIR_OK) return r;
+        } else if ((r = enqueue(d, s, size, true)) != PIR_OK) {
+            return r;
+        }
+        return hipEventRecord(s.done, s.stream) == hipSuccess ? PIR_OK : PIR_ERR_DEVICE;
     }
 
     pir_status setup_slot(DbQueue& d, Slot& s) {
@@ -140,6 +186,11 @@ struct pir_server {
         if (hipHostMalloc((void**)&s.h_Q, (size_t)mb * d.C * 4, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&s.h_O, (size_t)mb * d.R * 4, hipHostMallocDefault) != hipSuccess)
             return PIR_ERR_NO_MEMORY;
+        if (hipHostMalloc((void**)&s.h_flag, 64, hipHostMallocDefault) != hipSuccess)
+            return PIR_ERR_NO_MEMORY;
+        __atomic_store_n(s.h_flag, 0u, __ATOMIC_RELAXED);
+        if (hipHostGetDevicePointer((void**)&s.d_flag, s.h_flag, 0) != hipSuccess)
+            return PIR_ERR_DEVICE;
         memset(s.h_Q, 0, (size_t)mb * d.C * 4);
         // Every power-of-two size the slot launches (small batches take a
         // different kernel path with its own workspace need).
@@ -157,7 +208,7 @@ struct pir_server {
         for (uint32_t k = 0; k < nb; ++k) {
             if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return PIR_ERR_DEVICE;
-            pir_status r = enqueue(d, s, 1u << k);
+            pir_status r = enqueue(d, s, 1u << k, (1u << k) < kDirectCopies);
             hipGraph_t g = nullptr;
             const hipError_t e = hipStreamEndCapture(s.stream, &g);
             if (r != PIR_OK) return r;
@@ -182,6 +233,7 @@ struct pir_server {
         if (s.h_Q) (void)hipHostFree(s.h_Q);
         if (s.h_O) (void)hipHostFree(s.h_O);
         if (s.done) (void)hipEventDestroy(s.done);
+        if (s.h_flag) (void)hipHostFree(s.h_flag);
         if (s.stream) (void)hipStreamDestroy(s.stream);
         s = Slot();
     }
@@ -213,7 +265,7 @@ struct pir_server {
             // Launch while the device takes more batches: each time, the
             // database whose oldest request has waited longest, with
             // everything it has queued (up to max_batch and the budget).
-            while (fault == PIR_OK && (cfg.max_inflight == 0 || inflight.size() < cfg.max_inflight)) {
+            while (fault == PIR_OK && (cfg.max_inflight == 0 || n_computing < cfg.max_inflight)) {
                 size_t pick = nd;
                 for (size_t i = 0; i < nd; ++i) {
                     DbQueue& c = dbs[i];
@@ -247,15 +299,8 @@ struct pir_server {
                 // Pack the queries (query-major rows of C words) and launch.
                 for (uint32_t b = 0; b < n; ++b)
                     memcpy(s->h_Q + (size_t)b * d.C, s->batch[b]->h_q, d.C * 4);
-                pir_status st = PIR_OK;
-                if (cfg.use_graphs) {
-                    if (hipGraphLaunch(s->exec[log2_floor(size)], s->stream) != hipSuccess)
-                        st = PIR_ERR_DEVICE;
-                } else {
-                    st = enqueue(d, *s, size);
-                }
-                if (st == PIR_OK && hipEventRecord(s->done, s->stream) != hipSuccess)
-                    st = PIR_ERR_DEVICE;
+                __atomic_store_n(s->h_flag, 0u, __ATOMIC_RELAXED);   // raised by this launch
+                const pir_status st = launch(d, *s, size);
                 lk.lock();
                 if (st != PIR_OK) {
                     fault = st;
@@ -266,6 +311,8 @@ struct pir_server {
                     cv_done.notify_all();
                     break;
                 }
+                s->computing = true;
+                ++n_computing;
                 inflight.push_back(s);
                 launched = true;
                 cv_done.notify_all();
@@ -289,6 +336,15 @@ struct pir_server {
         }
     }
 
+    // The batch's kernels have finished (its answers may still be copying
+    // out): it no longer counts against max_inflight.  Caller holds the lock.
+    void kernels_done(Slot& s) {
+        if (!s.computing) return;
+        s.computing = false;
+        --n_computing;
+        cv_sched.notify_all();
+    }
+
     void complete(Slot* s) {
         DbQueue* d = &dbs[s->db];
         const uint64_t t = now_ns();
@@ -301,6 +357,7 @@ struct pir_server {
         std::lock_guard<std::mutex> lk(mu);
         n_done += s->batch.size();
         s->batch.clear();
+        kernels_done(*s);
         s->busy = false;
         used -= s->cost;
         --d->inflight;
@@ -322,6 +379,12 @@ struct pir_server {
             }
             bool any = false;
             for (Slot* s : watch) {
+                // Only this thread clears `computing` once the slot is in flight.
+                if (s->computing && __atomic_load_n(s->h_flag, __ATOMIC_ACQUIRE) == 1u) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    kernels_done(*s);
+                    any = true;
+                }
                 const hipError_t e = hipEventQuery(s->done);
                 if (e == hipSuccess) {
                     complete(s);
@@ -330,6 +393,7 @@ struct pir_server {
                     std::lock_guard<std::mutex> lk(mu);
                     fault = PIR_ERR_DEVICE;
                     fail_batch(*s);
+                    kernels_done(*s);
                     s->busy = false;
                     used -= s->cost;
                     --dbs[s->db].inflight;

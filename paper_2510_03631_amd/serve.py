@@ -28,8 +28,9 @@ def _host_words(a: np.ndarray, n: int, name: str) -> np.ndarray:
 class Server:
     """Continuous-batching PIR server over open :class:`Database` objects.
 
-    ``max_inflight`` caps the batches on the device over all databases
-    (0: only ``slots_per_db`` bounds them).  Under load the cap keeps
+    ``max_inflight`` caps the batches with kernels pending over all
+    databases; one that only copies its answers out no longer counts (0: only
+    ``slots_per_db`` bounds them).  Under load the cap keeps
     requests queued while the device is busy, so they leave in larger
     batches; the database with the longest-waiting request goes first.
     """

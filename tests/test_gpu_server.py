@@ -101,6 +101,31 @@ def test_inflight_cap(env, max_inflight):
         assert st["batches"] < st["completed"]   # queued work left in batches
 
 
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_held_queue_leaves_as_one_batch(env, use_graphs):
+    # Queries queued while their database is paused leave as one batch of
+    # 16 on resume: the size whose copies run as plain stream copies around
+    # the graph of kernels (batches of 8 or more); the answers equal the
+    # oracle's, twice in a row.
+    from paper_2510_03631_amd.serve import Server
+    banner(f"server held queue -> one batch of 16, graphs={use_graphs}")
+    dbs, queries, expected = env["dbs"], env["queries"], env["expected"]
+    with Server(dbs, max_batch=16, slots_per_db=2, use_graphs=use_graphs) as srv:
+        for rep in range(2):
+            srv.pause(2)
+            s0 = srv.stats()
+            outs = []
+            for i in range(16):
+                outs.append(np.zeros(SHAPES[2][0], dtype=np.uint32))
+                srv.submit(2, queries[2][i + rep], outs[-1])
+            srv.resume(2)
+            srv.drain()
+            s1 = srv.stats()
+            assert s1["batches"] - s0["batches"] == 1, rep
+            for i in range(16):
+                assert np.array_equal(outs[i], expected[2][i + rep]), (rep, i)
+
+
 def test_memory_budget_admission(env):
     from paper_2510_03631_amd.serve import Server
     banner("server tiny memory budget")
