@@ -64,7 +64,7 @@ struct Req {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    uint32_t* h_flag = nullptr;   // pinned word: 1 once the batch's kernels have run
+    uint32_t* h_flag = nullptr;   // pinned word: 1 once a large batch's kernels have run
     uint32_t* d_flag = nullptr;   // the same word as the device addresses it
     uint32_t* h_Q = nullptr;   // pinned, max_batch x C (query-major)
     uint32_t* h_O = nullptr;   // pinned, max_batch x R (answer-major)
@@ -155,11 +155,14 @@ struct pir_server {
         r = size == 1 ? pir_answer(d.db, s.d_Q, s.d_O, s.d_ws, s.ws_bytes, st)
                       : pir_answer_batch_qmajor(d.db, s.d_Q, size, s.d_O, s.d_ws, s.ws_bytes, st);
         if (r != PIR_OK) return r;
-        // Kernels done: raise the slot's host flag, so the scheduler stops
-        // counting the batch against max_inflight.
+        if (copies) return copy_out(d, s, size);
+        // Kernels done, answers not yet copied out: raise the slot's host
+        // flag, so the scheduler stops counting the batch against
+        // max_inflight.  (A batch with its copies in the graph counts until
+        // it completes; it is small, and skipping this launch keeps its
+        // latency down.)
         k_raise_flag<<<1, 64, 0, st>>>(s.d_flag);
-        if (hipGetLastError() != hipSuccess) return PIR_ERR_DEVICE;
-        return copies ? copy_out(d, s, size) : PIR_OK;
+        return hipGetLastError() == hipSuccess ? PIR_OK : PIR_ERR_DEVICE;
     }
 
     // One batch: its copies and kernels (a graph replay or direct launches),
@@ -218,6 +221,12 @@ struct pir_server {
                 return PIR_ERR_DEVICE;
             // One replay now, so first requests do not pay for lazy setup.
             if (hipGraphLaunch(s.exec[k], s.stream) != hipSuccess) return PIR_ERR_DEVICE;
+        }
+        // Likewise one round of the stream copies of large batches.
+        if (mb >= kDirectCopies) {
+            pir_status r = copy_in(d, s, mb);
+            if (r == PIR_OK) r = copy_out(d, s, mb);
+            if (r != PIR_OK) return r;
         }
         return hipStreamSynchronize(s.stream) == hipSuccess ? PIR_OK : PIR_ERR_DEVICE;
     }
