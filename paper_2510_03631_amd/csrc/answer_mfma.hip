@@ -69,6 +69,7 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 typedef unsigned long long u64;
 
 constexpr uint32_t kCentreWord = 0x80808080u;
+constexpr int kCpolNT = 2;   // cache-policy operand of a load: nt (non-temporal) on gfx950
 constexpr int kKPad = 256;                    // QL rows are zero-padded to a multiple of this
 constexpr uint32_t kExactSpan = 1u << 17;     // columns one exact int32 accumulation may cover
 constexpr uint32_t kMaxExactCols = 1u << 23;  // D q < 2^64 and exact row sums
@@ -594,7 +595,7 @@ struct Ring {
 
 // Workgroup w covers tile tile_of(w) and, with split-K, the k-tiles
 // [split * kts, split * kts + kts) of its piece.
-template <class T, bool GATHER, int MODE>
+template <class T, bool GATHER, int MODE, bool NTD>
 __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restrict__ D,
                                                           uint64_t pitch,
                                                           const int8_t* __restrict__ QL,
@@ -652,7 +653,10 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
         uint8_t* dst = smem + (t % T::STAGES) * T::STAGE_BYTES + (wave + T::NW * i) * 1024;
         const uint8_t* p = i < T::A_LOADS ? src[i] + min(k0 + seg_off[i], C - 16u)
                                           : src[i] + ql_col(k0);   // BK divides 128
-        __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)dst, 16, 0, 0);
+        if (NTD && i < T::A_LOADS)   // D read once: non-temporal
+            __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)dst, 16, 0, kCpolNT);
+        else
+            __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)dst, 16, 0, 0);
     };
 
     i32x16 acc[T::TM][T::TN];
@@ -927,12 +931,24 @@ uint32_t g_cus = 256;       // compute units of the device (set at init)
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// With one column tile (a batch no wider than the tile), each byte of D is
+// read by one workgroup only, so D's loads are marked non-temporal and do
+// not evict the limb planes every workgroup re-reads.
 template <class T, bool GATHER, int MODE>
 pir_status launch_ring_mode(const Gemm& g, uint32_t n_tiles, uint32_t m_tiles, hipStream_t s) {
     const uint64_t blocks = (uint64_t)n_tiles * m_tiles * g.splits;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
-    k_gemm_ring<T, GATHER, MODE><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
-        g.db->D, g.db->pitch, g.QL, g.Cp, n_tiles, m_tiles, g.kts, g.e);
+    bool nt = false;
+    if constexpr (!GATHER) {
+        if (n_tiles == 1) {
+            nt = true;
+            k_gemm_ring<T, false, MODE, true><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
+                g.db->D, g.db->pitch, g.QL, g.Cp, n_tiles, m_tiles, g.kts, g.e);
+        }
+    }
+    if (!nt)
+        k_gemm_ring<T, GATHER, MODE, false><<<(uint32_t)blocks, T::THREADS, T::LDS_BYTES, s>>>(
+            g.db->D, g.db->pitch, g.QL, g.Cp, n_tiles, m_tiles, g.kts, g.e);
     PIR_LAUNCH_CHECK();
     return PIR_OK;
 }
@@ -958,9 +974,16 @@ pir_status launch_ring(const Gemm& g, hipStream_t s) {
 template <class T>
 pir_status set_ring_lds() {
     const void* fns[] = {
-        (const void*)k_gemm_ring<T, false, kFinal32>, (const void*)k_gemm_ring<T, true, kFinal32>,
-        (const void*)k_gemm_ring<T, false, kPart32>,  (const void*)k_gemm_ring<T, true, kPart32>,
-        (const void*)k_gemm_ring<T, false, kPart64>,  (const void*)k_gemm_ring<T, false, kFinalModP>,
+        (const void*)k_gemm_ring<T, false, kFinal32, false>,
+        (const void*)k_gemm_ring<T, true, kFinal32, false>,
+        (const void*)k_gemm_ring<T, false, kPart32, false>,
+        (const void*)k_gemm_ring<T, true, kPart32, false>,
+        (const void*)k_gemm_ring<T, false, kPart64, false>,
+        (const void*)k_gemm_ring<T, false, kFinalModP, false>,
+        (const void*)k_gemm_ring<T, false, kFinal32, true>,
+        (const void*)k_gemm_ring<T, false, kPart32, true>,
+        (const void*)k_gemm_ring<T, false, kPart64, true>,
+        (const void*)k_gemm_ring<T, false, kFinalModP, true>,
     };
     for (const void* f : fns)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES) !=
