@@ -5,9 +5,11 @@ The oracle cannot recompute gigabyte products in test time, so each case
 checks (a) sampled rows element by element against the oracle, (b) the LWE
 decode of every row, which recovers the queried column only if every answer
 word is right to within the noise margin (and the sampled rows pin it
-exactly), and (c) Freivalds' randomized check of whole products over a slab
-of rows.  Databases are drawn on the device with a seeded torch generator;
-the rows a check needs are copied back to the host.
+exactly), and (c) Freivalds' randomized check of every whole product over
+all rows, 16 trials each: a wrong word anywhere survives a trial with
+probability at most 1/2, so all 16 with at most 2^-16.  Databases are drawn
+on the device with a seeded torch generator and copied back to the host
+whole for the checks.
 """
 import time
 
@@ -46,6 +48,7 @@ def spectrum(qp, tune):
     shape = workload.CONFIGS["spectrum_1q"]
     R, C, n = shape.rows, shape.cols, shape.n
     D = workload.device_db(R, C, workload.SEED_BASE + 1, "cuda")
+    Dh = D.cpu().numpy()
     g = workload.rng(workload.SEED_BASE + 1)
     A = workload.uniform_u32(g, (C, n))
     Ad = to_dev_u32(A)
@@ -54,7 +57,7 @@ def spectrum(qp, tune):
     H = db.setup_hint(Ad)
     torch.cuda.synchronize()
     _step("database, A and hint ready", t0)
-    yield dict(D=D, A=A, Ad=Ad, db=db, H=H, g=g, R=R, C=C, n=n)
+    yield dict(D=D, Dh=Dh, A=A, Ad=Ad, db=db, H=H, g=g, R=R, C=C, n=n)
     db.close()
     del D, Ad, H
     torch.cuda.empty_cache()
@@ -62,16 +65,14 @@ def spectrum(qp, tune):
 
 def test_spectrum_hint(spectrum):
     t0 = time.perf_counter()
-    banner("spectrum hint: sampled rows + Freivalds slab")
+    banner("spectrum hint: sampled rows + 16 Freivalds trials over all rows")
     s = spectrum
     H = to_host_u32(s["H"])
     rows = sample_rows(s["R"], 48, 1)
-    Drows = s["D"][rows].cpu().numpy()
-    assert np.array_equal(H[rows], oracle.hint(Drows, s["A"]))
+    assert np.array_equal(H[rows], oracle.hint(s["Dh"][rows], s["A"]))
     _step("sampled hint rows exact", t0)
-    slab = s["D"][:2048].cpu().numpy()
-    assert oracle.freivalds(slab, s["A"], H[:2048], trials=4, seed=3)
-    _step("Freivalds on rows 0..2047", t0)
+    assert oracle.freivalds(s["Dh"], s["A"], H, trials=16, seed=3)
+    _step("Freivalds, 16 trials, all rows", t0)
 
 
 def test_spectrum_single_query(spectrum):
@@ -107,7 +108,7 @@ def test_spectrum_batch64(spectrum):
     Qd = to_dev_u32(Q)
     out = to_host_u32(s["db"].answer_batch(Qd))
     rows = sample_rows(s["R"], 128, 21)
-    assert np.array_equal(out[rows], oracle.answer_batch(s["D"][rows].cpu().numpy(), Q))
+    assert np.array_equal(out[rows], oracle.answer_batch(s["Dh"][rows], Q))
     _step("sampled rows exact", t0)
     H = to_host_u32(s["H"])
     for b in range(64):
@@ -115,12 +116,11 @@ def test_spectrum_batch64(spectrum):
         assert np.array_equal(oracle.lwe_decode(out[:, b], H, dr.s[b]),
                               s["D"][:, col].cpu().numpy()), b
     _step("all 64 queries decode on every row", t0)
-    slab = s["D"][-2048:].cpu().numpy()
-    assert oracle.freivalds(slab, Q, out[-2048:], trials=4, seed=5)
+    assert oracle.freivalds(s["Dh"], Q, out, trials=16, seed=5)
     for b in (0, 63):
         single = to_host_u32(s["db"].answer(to_dev_u32(np.ascontiguousarray(Q[:, b]))))
         assert np.array_equal(single, out[:, b])
-    _step("Freivalds slab + batch column == single answer", t0)
+    _step("Freivalds (16 trials, all rows) + batch column == single answer", t0)
 
 
 def test_large_batch256_update(qp, tune):
@@ -150,20 +150,22 @@ def test_large_batch256_update(qp, tune):
     _step("batch and hint computed", t0)
     out = to_host_u32(out_d)
     H = to_host_u32(Hd)
+    Dh = D.cpu().numpy()
+    _step("database, answers and hint copied to the host", t0)
     rows = sample_rows(R, 24, 31)
-    Drows = D[rows].cpu().numpy()
-    assert np.array_equal(out[rows], oracle.answer_batch(Drows, Q))
+    assert np.array_equal(out[rows], oracle.answer_batch(Dh[rows], Q))
     _step("batch sampled rows exact", t0)
     hrows = rows[:12]
-    assert np.array_equal(H[hrows], oracle.hint(D[hrows].cpu().numpy(), A))
+    assert np.array_equal(H[hrows], oracle.hint(Dh[hrows], A))
     _step("hint sampled rows exact", t0)
     for b in range(4):
         col = int(dr.col[b])
-        assert np.array_equal(oracle.lwe_decode(out[:, b], H, dr.s[b]), D[:, col].cpu().numpy())
+        assert np.array_equal(oracle.lwe_decode(out[:, b], H, dr.s[b]), Dh[:, col])
     _step("4 LWE queries decode on every row", t0)
-    slab = D[:256].cpu().numpy()
-    assert oracle.freivalds(slab, Q, out[:256], trials=2, seed=7)
-    _step("Freivalds rows 0..255", t0)
+    assert oracle.freivalds(Dh, Q, out, trials=16, seed=7)
+    _step("batch: Freivalds, 16 trials, all rows", t0)
+    assert oracle.freivalds(Dh, A, H, trials=16, seed=8)
+    _step("hint: Freivalds, 16 trials, all rows", t0)
 
     # -- refresh 1% of the rows and update the hint incrementally
     m = workload.update_count(R)
@@ -175,23 +177,27 @@ def test_large_batch256_update(qp, tune):
     db.hint_update_rows(urows_d, Ad, Hd)
     torch.cuda.synchronize()
     _step("rows rewritten, hint updated", t0)
+    Dh = oracle.update_rows(Dh, urows, new)
+    assert np.array_equal(D.cpu().numpy(), Dh)      # the refresh itself, every row
+    _step("refreshed database equals the oracle's update", t0)
     H2 = to_host_u32(Hd)
     keep = np.ones(R, dtype=bool)
     keep[urows.astype(np.int64)] = False
     assert np.array_equal(H2[keep], H[keep])        # untouched rows unchanged
     pick = urows[np.random.default_rng(3).choice(m, size=12, replace=False)].astype(np.int64)
     pick.sort()
-    Dpick = D[pick].cpu().numpy()
-    assert np.array_equal(Dpick, new[np.searchsorted(urows, pick)])
-    assert np.array_equal(H2[pick], oracle.hint(Dpick, A))
+    assert np.array_equal(H2[pick], oracle.hint(Dh[pick], A))
     _step("updated hint rows exact, other rows untouched", t0)
+    assert oracle.freivalds(Dh, A, H2, trials=16, seed=9)
+    _step("updated hint: Freivalds, 16 trials, all rows", t0)
     out2 = to_host_u32(db.answer_batch(Qd))
     both = np.unique(np.concatenate([pick, rows]))
-    assert np.array_equal(out2[both], oracle.answer_batch(D[both].cpu().numpy(), Q))
+    assert np.array_equal(out2[both], oracle.answer_batch(Dh[both], Q))
     for b in range(4):
         col = int(dr.col[b])
-        assert np.array_equal(oracle.lwe_decode(out2[:, b], H2, dr.s[b]), D[:, col].cpu().numpy())
-    _step("answers after the refresh exact and decodable", t0)
+        assert np.array_equal(oracle.lwe_decode(out2[:, b], H2, dr.s[b]), Dh[:, col])
+    assert oracle.freivalds(Dh, Q, out2, trials=16, seed=10)
+    _step("answers after the refresh: sampled rows exact, decodable, Freivalds all rows", t0)
     db.close()
-    del D, Ad, Hd, Qd, out_d
+    del D, Dh, Ad, Hd, Qd, out_d
     torch.cuda.empty_cache()
