@@ -100,29 +100,73 @@ def spread(us, nbytes: int) -> dict:
             "median_gbs_db": round(nbytes / (med * 1e-6) / 1e9, 1)}
 
 
-def cpu_baseline(R: int, C: int, seconds: float = 10.0):
-    """Oracle single-query Answer on a bounded sample of the workload."""
+def _median_rate(fn, runs: int, seconds: float) -> tuple:
+    """Median over ``runs`` of (passes per second), each run repeating ``fn``
+    for at least ``seconds``; also returns the total passes."""
     import numpy as np
+    rates, total = [], 0
+    fn()   # load + warm
+    for _ in range(runs):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            fn()
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+        rates.append(n / el)
+        total += n
+    return float(np.median(rates)), total
+
+
+def cpu_baseline(R: int, C: int, n: int, runs: int = 3):
+    """The oracle, as it stands, on bounded row samples of the spectrum
+    workload (32768 x 32768 bytes), scaled to the full shape: the single-query
+    Answer on all host threads (the headline figure) and on one thread, the
+    64-query batch and the n = 1024 hint.  Each figure is the median of
+    ``runs`` timed runs."""
     import oracle
     import workload
     g = workload.rng(workload.SEED_BASE + 99)
-    rows = min(R, 2048)
-    D = workload.db_bytes(g, rows, C)
+    threads = oracle.num_threads()
+    D = workload.db_bytes(g, min(R, 2048), C)
     q = workload.uniform_u32(g, C)
-    oracle.answer(D, q)   # load + warm
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.answer(D, q)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    gbs = rows * C * n / el / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{rows} x {C} uint8 rows of the database, one query, "
-                      f"{n} passes in {el:.1f} s (plain C loops, OpenMP)"}
+    Q = workload.uniform_u32(g, (C, 64))
+    A = workload.uniform_u32(g, (C, n))
+
+    rate, passes = _median_rate(lambda: oracle.answer(D, q), runs, 2.0)
+    gbs = D.shape[0] * C * rate / 1e9
+    out = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"single-query Answer on {D.shape[0]} x {C} rows of the database "
+                     f"(plain C loops, OpenMP, {threads} threads), median of {runs} runs "
+                     f"of 2 s ({passes} passes)"}
+
+    d1 = D[:256]
+    oracle.set_threads(1)
+    try:
+        rate1, passes1 = _median_rate(lambda: oracle.answer(d1, q), runs, 1.5)
+    finally:
+        oracle.set_threads(threads)
+    out["single_thread"] = {"gbs": round(d1.shape[0] * C * rate1 / 1e9, 3), "cores": 1,
+                            "sample": f"{d1.shape[0]} x {C} rows, median of {runs} runs "
+                                      f"of 1.5 s ({passes1} passes)"}
+
+    db_ = D[:256]
+    rateb, passesb = _median_rate(lambda: oracle.answer_batch(db_, Q), runs, 1.5)
+    tb_full = R / db_.shape[0] / rateb
+    out["batch64"] = {"gbs_db": round(db_.shape[0] * C * rateb / 1e9, 3),
+                      "queries_per_s": round(64 / tb_full, 2),
+                      "s_per_batch_full": round(tb_full, 3), "cores": threads,
+                      "sample": f"{db_.shape[0]} x {C} rows x 64 queries, median of {runs} "
+                                f"runs of 1.5 s ({passesb} passes), scaled to {R} rows"}
+
+    dh = D[:32]
+    rateh, passesh = _median_rate(lambda: oracle.hint(dh, A), runs, 1.5)
+    out["hint"] = {"s_full": round(R / dh.shape[0] / rateh, 2), "cores": threads,
+                   "sample": f"{dh.shape[0]} x {C} rows x n = {n}, median of {runs} runs "
+                             f"of 1.5 s ({passesh} passes), scaled to {R} rows"}
+    return out
 
 
 def lwe_queries_dev(C: int, n: int, B: int, seed: int, dev):
@@ -179,6 +223,12 @@ def large_bench(stream) -> dict:
     fi()
     _, evi = time_on_stream(fi, 3, stream)
     ti = evi / 3
+    # The same with A's limb planes prepared once (A is fixed; rows change).
+    planes = db.hint_planes(A)
+    fp = lambda: db.hint_update_rows_planes(rows, planes, n, H, ws=wsh)
+    fp()
+    _, evp = time_on_stream(fp, 5, stream)
+    tp = evp / 5
     db.close()
     res = {
         "workload": f"{R} x {C} uint8 (16 GiB), B={B}, n={n}, refresh of {m} rows",
@@ -189,9 +239,12 @@ def large_bench(stream) -> dict:
         "update_rows_ms": round(evu * 1e3, 3),
         "incremental_hint_ms": round(ti * 1e3, 3),
         "incremental_hint_mfma_frac": round(8.0 * m * C * n / ti / 1e12 / INT8_PEAK_TOPS, 4),
+        "incremental_hint_planes_ms": round(tp * 1e3, 3),
+        "incremental_hint_planes_mfma_frac": round(8.0 * m * C * n / tp / 1e12 / INT8_PEAK_TOPS,
+                                                   4),
         "hint_fraction_recomputed": round(m / R, 4),
     }
-    del D, Q, out, A, H, new, wsb, wsh
+    del D, Q, out, A, H, new, wsb, wsh, planes
     torch.cuda.empty_cache()
     return res
 
@@ -432,8 +485,11 @@ def serving_bench(args) -> dict:
     def sweep(srv, rates, seed_off):
         runs = []
         for rate in rates:
-            t, w, qs = trace(rate, 2.0, int(rate) + seed_off)
+            # Rates near saturation run longer: a stall there turns into a
+            # queue, and a short window can miss it.
+            t, w, qs = trace(rate, 5.0 if rate >= 200000.0 else 2.0, int(rate) + seed_off)
             runs.append(serving_run(srv, t, w, qs))
+            log(f"serving sweep: {rate:.0f} q/s offered, p99 {runs[-1]['p99_ms']} ms")
             if runs[-1]["p99_ms"] > p99_bound:
                 break   # past saturation: higher rates only queue longer
         ok = [r["achieved_qps"] for r in runs if r["p99_ms"] <= p99_bound]
@@ -441,15 +497,19 @@ def serving_bench(args) -> dict:
 
     with Server(dbs, max_batch=64, slots_per_db=3, mem_budget_bytes=budget,
                 max_inflight=inflight) as srv:
-        # Warm-up, untimed: the design rate, then a short burst that takes
-        # every batch size and copy path once (first uses in a process
-        # otherwise add milliseconds to the first loaded second).
-        t, w, qs = trace(workload.SERVING_RATE, 1.0, 1)
-        serving_run(srv, t, w, qs)
+        # Warm-up, untimed: a short burst that takes every batch size and
+        # copy path once (first uses in a process otherwise add milliseconds
+        # to the first loaded second), then the design rate for
+        # --serving-warmup seconds; the measured window follows.
         t, w, qs = trace(200000.0, 0.5, 3)
         serving_run(srv, t, w, qs)
+        t, w, qs = trace(workload.SERVING_RATE, args.serving_warmup, 1)
+        serving_run(srv, t, w, qs)
+        log(f"serving: {args.serving_seconds:.0f} s at {workload.SERVING_RATE:.0f} q/s")
         t, w, qs = trace(workload.SERVING_RATE, args.serving_seconds, 2)
         out["at_2000qps"] = serving_run(srv, t, w, qs)
+        out["at_2000qps"]["warmup_s"] = args.serving_warmup
+        out["at_2000qps"]["window_s"] = args.serving_seconds
         out["batched_sweep"], out["batched_max_qps_at_p99_bound"] = sweep(
             srv, (8000.0, 20000.0, 40000.0, 80000.0, 160000.0, 240000.0, 320000.0, 360000.0,
                   400000.0, 440000.0, 480000.0), 0)
@@ -527,7 +587,7 @@ def profile_mode(args, dev, stream) -> int:
             del a, b
             torch.cuda.empty_cache()
         return 0
-    if args.profile == "update":
+    if args.profile in ("update", "update_planes"):
         # The refresh workload: 1% of the rows of the 16 GiB database
         # rewritten, then the incremental hint over those rows.
         big = workload.CONFIGS["large_b256"]
@@ -544,6 +604,9 @@ def profile_mode(args, dev, stream) -> int:
         new = workload.device_db(m, C, workload.SEED_BASE + 8, dev)
         db.update_rows(rows, new)
         fn = lambda: db.hint_update_rows(rows, A, H, ws=ws)
+        if args.profile == "update_planes":   # A's limb planes prepared once
+            planes = db.hint_planes(A)
+            fn = lambda: db.hint_update_rows_planes(rows, planes, n, H, ws=ws)
     else:
         D = workload.device_db(R, C, workload.SEED_BASE + 1, dev)
         db = qp.Database(D)
@@ -559,7 +622,7 @@ def profile_mode(args, dev, stream) -> int:
         out = torch.empty((R, B), dtype=torch.int32, device=dev)
         ws = db.workspace(B)
         fn = lambda: db.answer_batch(Q, out=out, ws=ws)
-    elif args.profile != "update":
+    elif args.profile not in ("update", "update_planes"):
         A = workload.device_u32((C, n), workload.SEED_BASE + 4, dev)
         H = torch.empty((R, n), dtype=torch.int32, device=dev)
         ws = db.workspace(n)
@@ -625,10 +688,14 @@ def main() -> int:
     ap.add_argument("--no-ftr", action="store_true")
     ap.add_argument("--no-oop", action="store_true")
     ap.add_argument("--no-client", action="store_true")
-    ap.add_argument("--serving-seconds", type=float, default=8.0)
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
+                    help="measured window at the design rate (2000 q/s)")
+    ap.add_argument("--serving-warmup", type=float, default=10.0,
+                    help="untimed seconds at the design rate before the window")
     ap.add_argument("--profile",
                     help="run only one kernel family (for rocprofv3 runs) and exit: answer, "
-                         "batchB, hint, update (incremental hint, 16 GiB), calibrate, intmm, "
+                         "batchB, hint, update (incremental hint, 16 GiB), update_planes (the same "
+                         "from prepared limb planes), calibrate, intmm, "
                          "or chorB / oopB / ftrB / clientB with B queries")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -796,8 +863,8 @@ def main() -> int:
         result["serving"] = serving_bench(args)
 
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ~10 s")
-        result["cpu_baseline"] = cpu_baseline(R, C)
+        log("cpu baseline (oracle) ~20 s")
+        result["cpu_baseline"] = cpu_baseline(R, C, n)
     if db._h is not None:
         db.close()
     print(json.dumps(result), flush=True)

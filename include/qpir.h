@@ -55,7 +55,10 @@ typedef enum pir_status {
     PIR_ERR_SHAPE = 2,         /* sizes that do not fit the handle or limits */
     PIR_ERR_NO_MEMORY = 3,     /* device or host allocation failed */
     PIR_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
-    PIR_ERR_UNSUPPORTED = 5,   /* device is not gfx950 */
+    PIR_ERR_UNSUPPORTED = 5,   /* device is not gfx950, or no kernel serves this
+                                  combination (field form on gathered rows or on
+                                  an unaligned database beyond 4 queries, a
+                                  variant the database cannot run) */
     PIR_ERR_WORKSPACE = 6,     /* workspace missing, too small or misaligned */
     PIR_ERR_BUSY = 7,          /* serving queue full: request not admitted */
     PIR_ERR_TIMEOUT = 8        /* wait ended before the request completed */
@@ -210,6 +213,36 @@ pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m
                                 void* d_ws, size_t ws_bytes, pir_stream_t stream);
 
 /*
+ * The incremental hint from limb planes of A prepared once.  A is fixed for
+ * a deployment (the public LWE matrix), while rows are refreshed every
+ * validity interval (Section 4.2); pir_hint_update_rows re-derives A's
+ * 8-bit limb planes on every call, and these entry points let a caller
+ * derive them once (the offline work of Section 5.3 kept off the refresh
+ * path).
+ *
+ * pir_hint_planes_bytes: bytes of the prepared planes of n columns of A for
+ *   databases with this handle's column count (0 for a bad handle).
+ * pir_hint_planes: write them.
+ *   d_A      C x n words, row-major (as for pir_setup_hint).
+ *   d_planes device buffer of pir_hint_planes_bytes(db, n) bytes, 256-byte
+ *            aligned, caller-owned; its content is opaque and stays valid
+ *            for any handle with the same column count until A changes.
+ * pir_hint_update_rows_planes: pir_hint_update_rows with A given by its
+ *   prepared planes (same results, bit for bit).
+ *   d_planes, planes_bytes  as written by pir_hint_planes for this n.
+ *   d_ws     workspace of pir_workspace_bytes(db, n) bytes.
+ * Errors: PIR_ERR_INVALID_ARG (null pointer, n == 0), PIR_ERR_SHAPE,
+ * PIR_ERR_WORKSPACE (planes or workspace missing, too small or misaligned).
+ */
+size_t pir_hint_planes_bytes(const pir_db_t* db, uint32_t n);
+pir_status pir_hint_planes(pir_db_t* db, const uint32_t* d_A, uint32_t n, void* d_planes,
+                           size_t planes_bytes, pir_stream_t stream);
+pir_status pir_hint_update_rows_planes(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
+                                       const void* d_planes, size_t planes_bytes, uint32_t n,
+                                       uint32_t* d_H, void* d_ws, size_t ws_bytes,
+                                       pir_stream_t stream);
+
+/*
  * Client side of LWE PIR on the GPU (Definition 1: the client builds the
  * queries and reconstructs the block from the responses), for B queries at
  * once.  No handle needed; runs on the current device (gfx950).
@@ -346,7 +379,11 @@ typedef struct pir_server_config {
     uint32_t max_batch;         /* largest batch per launch: power of two, 1..1024 */
     uint32_t slots_per_db;      /* batches in flight per database, 1..16 */
     uint64_t mem_budget_bytes;  /* device bytes of all batches in flight (queries,
-                                   answers, workspace), > 0 */
+                                   answers, workspace), > 0.  It gates launches; it
+                                   does not bound what pir_server_start allocates
+                                   (every slot holds buffers for max_batch queries
+                                   and a workspace for the largest batch; see
+                                   pir_server_stats.device_bytes) */
     uint32_t max_queue;         /* queued requests per database before submit
                                    returns PIR_ERR_BUSY; 0 = unbounded */
     uint32_t use_graphs;        /* 1: replay captured HIP graphs; 0: direct launches */
@@ -362,6 +399,7 @@ typedef struct pir_server_stats {
     uint64_t batches, batched_queries;           /* launched batches and their queries */
     uint64_t budget_bytes, peak_inflight_bytes;  /* admission budget and its high-water mark */
     uint64_t p50_ns, p99_ns, max_ns;             /* latency of completed requests */
+    uint64_t device_bytes;                       /* device memory the slots hold */
 } pir_server_stats;
 
 /* Create a server on the current device (no threads yet). */
@@ -387,7 +425,10 @@ uint64_t pir_server_now_ns(void);
 /* Block until the request completes (PIR_OK), fails (PIR_ERR_DEVICE) or
  * `timeout_ns` passes (PIR_ERR_TIMEOUT; UINT64_MAX waits forever). */
 pir_status pir_server_wait(pir_server_t* server, uint64_t ticket, uint64_t timeout_ns);
-/* Block until every submitted request has completed or failed. */
+/* Block until every submitted request has completed or failed (PIR_OK, or
+ * PIR_ERR_DEVICE if any failed).  Requests queued for a paused database wait
+ * for its resume, so while one is held the call returns PIR_ERR_BUSY instead
+ * of blocking; the held requests stay queued. */
 pir_status pir_server_drain(pir_server_t* server);
 /* Stop launching batches for one database and wait for its batches in
  * flight, e.g. around pir_update_rows / pir_hint_update_rows; queued
@@ -410,8 +451,9 @@ pir_status pir_server_latencies(pir_server_t* server, uint64_t first, uint64_t c
 pir_status pir_server_replay(pir_server_t* server, uint64_t n, const uint64_t* offsets_ns,
                              const uint32_t* db_index, const uint32_t* const* h_q,
                              uint32_t* const* h_answer, uint64_t* first_ticket);
-/* Finish every queued and running request, stop the threads and free the
- * server's buffers (not the databases). */
+/* Finish every queued and running request (paused databases are resumed
+ * for it), stop the threads and free the server's buffers (not the
+ * databases). */
 pir_status pir_server_destroy(pir_server_t* server);
 
 #ifdef __cplusplus

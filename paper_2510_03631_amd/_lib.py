@@ -43,7 +43,7 @@ class ServerConfig(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "submitted", "completed", "failed", "rejected", "batches", "batched_queries",
-        "budget_bytes", "peak_inflight_bytes", "p50_ns", "p99_ns", "max_ns")]
+        "budget_bytes", "peak_inflight_bytes", "p50_ns", "p99_ns", "max_ns", "device_bytes")]
 
 
 # name -> (restype, argtypes); mirrors include/qpir.h
@@ -61,6 +61,9 @@ SIGNATURES = {
     "pir_hint_update_rows": (_ST, [_P, _P, _U32, _P, _U32, _P, _P, _SZ, _P]),
     "pir_answer_batch_qmajor": (_ST, [_P, _P, _U32, _P, _P, _SZ, _P]),
     "pir_answer_batch_modp": (_ST, [_P, _P, _U32, _U32, _P, _P, _SZ, _P]),
+    "pir_hint_planes_bytes": (_SZ, [_P, _U32]),
+    "pir_hint_planes": (_ST, [_P, _P, _U32, _P, _SZ, _P]),
+    "pir_hint_update_rows_planes": (_ST, [_P, _P, _U32, _P, _SZ, _U32, _P, _P, _SZ, _P]),
     "pir_variant_count": (_U32, [_U32]),
     "pir_variant_name": (ctypes.c_char_p, [_U32, _U32]),
     "pir_db_set_variant": (_ST, [_P, _U32, _U32]),
@@ -342,6 +345,39 @@ class Database:
         check(lib().pir_hint_update_rows(self.handle, rp, m, ap, n, hp, wp, wn,
                                          _stream_ptr(stream, self.device)),
               "pir_hint_update_rows")
+        return H
+
+    def hint_planes(self, A: torch.Tensor, out: torch.Tensor = None, stream=None):
+        """A's limb planes for the incremental hint (``pir_hint_planes``):
+        a uint8 device tensor, opaque, valid for databases with this column
+        count until A changes."""
+        n = int(A.shape[1])
+        ap = _ptr_words(A, "A", (self.cols, n), self.device)
+        nb = int(lib().pir_hint_planes_bytes(self.handle, n))
+        if out is None:
+            out = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        if out.dtype != torch.uint8 or out.numel() < nb or not out.is_contiguous():
+            raise ValueError(f"planes: expected a contiguous uint8 tensor of {nb} bytes")
+        check(lib().pir_hint_planes(self.handle, ap, n, out.data_ptr(), out.numel(),
+                                    _stream_ptr(stream, self.device)), "pir_hint_planes")
+        return out
+
+    def hint_update_rows_planes(self, rows: torch.Tensor, planes: torch.Tensor, n: int,
+                                H: torch.Tensor, stream=None, ws=None):
+        """``hint_update_rows`` with A given by :meth:`hint_planes`
+        (``pir_hint_update_rows_planes``)."""
+        m = int(rows.numel())
+        rp = _ptr_words(rows, "rows", (m,), self.device)
+        hp = _ptr_words(H, "H", (self.rows, n), self.device)
+        if planes.dtype != torch.uint8 or not planes.is_contiguous() or planes.device != self.device:
+            raise ValueError("planes: expected a contiguous uint8 tensor on the database's device")
+        if ws is None:
+            ws = self.workspace(n)
+        wp, wn = self._ws_args(ws)
+        check(lib().pir_hint_update_rows_planes(self.handle, rp, m, planes.data_ptr(),
+                                                planes.numel(), n, hp, wp, wn,
+                                                _stream_ptr(stream, self.device)),
+              "pir_hint_update_rows_planes")
         return H
 
 

@@ -371,14 +371,16 @@ __device__ inline uint32_t xcd_remap(uint32_t bid, uint32_t nblk) {
 }
 
 // Tile of a (remapped) workgroup index, split-major: within a split, tiles
-// go in groups of 8 row tiles so the ~32 workgroups an XCD runs at once
-// share D and QL tiles in its L2.
+// go in groups of `group` row tiles (8 over a whole database) so the ~32
+// workgroups an XCD runs at once share D and QL tiles in its L2.  Gathered
+// rows take every row tile of a column tile as one group: their few row
+// tiles then read each limb-plane tile together.
 struct TileId {
     uint32_t m, n, split;
 };
 
-__device__ inline TileId tile_of(uint32_t bid, uint32_t n_tiles, uint32_t m_tiles) {
-    constexpr uint32_t kGroup = 8;
+__device__ inline TileId tile_of(uint32_t bid, uint32_t n_tiles, uint32_t m_tiles,
+                                 uint32_t kGroup = 8) {
     const uint32_t tiles = n_tiles * m_tiles;
     TileId t;
     t.split = bid / tiles;
@@ -609,7 +611,8 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     const int wm = wave / T::WN;
     const int wn = wave % T::WN;
 
-    const TileId tl = tile_of(xcd_remap(blockIdx.x, gridDim.x), n_tiles, m_tiles);
+    const TileId tl = tile_of(xcd_remap(blockIdx.x, gridDim.x), n_tiles, m_tiles,
+                              GATHER ? m_tiles : 8u);
     const uint32_t m0 = tl.m * T::BM;
     const uint32_t n0 = tl.n * T::BN;
     const uint32_t ktiles_all = (C + T::BK - 1) / T::BK;
@@ -928,6 +931,7 @@ struct Gemm {
 };
 
 uint32_t g_cus = 256;       // compute units of the device (set at init)
+uint64_t g_max_grid_y = 65535;   // largest grid y extent of the device (set at init)
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
@@ -1258,6 +1262,9 @@ pir_status mfma_init() {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         cus > 0)
         g_cus = (uint32_t)cus;
+    int gy = 0;
+    if (hipDeviceGetAttribute(&gy, hipDeviceAttributeMaxGridDimY, dev) == hipSuccess && gy > 0)
+        g_max_grid_y = (uint64_t)gy;
     pir_status st;
     if ((st = set_ring_lds<Ring128x128S8>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring128x128K128S4>()) != PIR_OK) return st;
@@ -1288,44 +1295,78 @@ size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B) {
     return std::max(batch_layout(db, B, kVariants[kVarRing128]).total, few_workspace_bytes(db, B));
 }
 
-pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
-                             const uint32_t* rows, uint32_t m, uint32_t modulus, void* ws,
-                             size_t ws_bytes, hipStream_t s) {
+// Every choice and every check of a batched call, before anything is
+// enqueued: variant, layout, split plan, grid limits and the workspace bytes
+// the call touches.
+pir_status mfma_plan_batch(const pir_db_t* db, uint32_t B, const uint32_t* rows, uint32_t m,
+                           uint32_t modulus, bool planes, BatchPlan* plan) {
     const uint32_t C = (uint32_t)db->cols;
     const bool exact = modulus != 0;
-    if (exact && rows) return PIR_ERR_UNSUPPORTED;
+    if (exact && rows) return PIR_ERR_UNSUPPORTED;   // no gathered field form
     if (exact && C > kMaxExactCols) return PIR_ERR_SHAPE;
-    // The reported size is the contract for every kernel path.
-    if (!ws || ws_bytes < mfma_workspace_bytes(db, B) || ((uintptr_t)ws % kWsAlign))
-        return PIR_ERR_WORKSPACE;
+    if (exact && planes) return PIR_ERR_UNSUPPORTED;
 
     uint32_t v = (rows ? db->variant_rows : db->variant)[batch_bucket(B)];
     if (v == 0 || !variant_valid(db, B, v)) v = rows ? default_rows(db, B) : default_variant(db, B);
     if (rows && kVariants[v].kind == kFew) v = default_gemm(db, B);
+    // Pre-ingested planes are in the wide layout: matrix-core variants that read it.
+    if (planes && (kVariants[v].kind == kFew || kVariants[v].narrow)) v = default_gemm(db, B);
     if (exact && kVariants[v].kind != kRing && kVariants[v].kind != kFew)
         v = (B <= kFewDefault || (B <= kFewMax && !ring_ok(db))) ? kVarFew : default_gemm(db, B);
     if (exact && (kVariants[v].kind == kReg || kVariants[v].kind == kRoles ||
                   (kVariants[v].kind == kRing && !ring_ok(db))))
         return PIR_ERR_UNSUPPORTED;   // field form beyond kFewMax queries needs the ring kernels
-    if (kVariants[v].kind == kFew) return few_answer_batch(db, io, B, modulus, ws, ws_bytes, s);
 
+    BatchPlan P{};
+    P.variant = v;
+    if (kVariants[v].kind == kFew) {
+        P.few = true;
+        P.need = few_workspace_bytes(db, B);
+        *plan = P;
+        return PIR_OK;
+    }
     const VariantInfo& vi = kVariants[v];
     const BatchLayout L = batch_layout(db, B, vi);
-    if (!ws || ws_bytes < L.total || ((uintptr_t)ws % kWsAlign)) return PIR_ERR_WORKSPACE;
-    uint8_t* base = static_cast<uint8_t*>(ws);
-    int8_t* QL = reinterpret_cast<int8_t*>(base);
-    u64* colsum = reinterpret_cast<u64*>(base + L.colsum_off);
+    P.Bp = L.Bp;
+    P.N = L.N;
+    P.Cp = L.Cp;
+    P.colsum_off = L.colsum_off;
+    P.part_off = L.part_off;
+    if ((uint64_t)L.Cp / kIngJ > g_max_grid_y) return PIR_ERR_SHAPE;   // ingest grid
+    P.M = rows ? m : (uint32_t)db->rows;
+    const SplitPlan sp = plan_splits(P.M, L.N, C, vi, exact);
+    P.splits = sp.splits;
+    P.kts = sp.kts;
+    const uint64_t blocks = (uint64_t)ceil_div(L.N, vi.bn) * ceil_div(P.M, vi.bm) * sp.splits;
+    if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
+    P.need = L.part_off;
+    if (sp.splits > 1) {
+        const uint64_t n = (uint64_t)P.M * B;
+        if ((n + 255) / 256 > 0x7FFFFFFFull) return PIR_ERR_SHAPE;   // k_finish grid
+        P.need += (size_t)sp.splits * P.M * B * 8;
+        if (P.need > L.total) return PIR_ERR_WORKSPACE;   // cannot happen: the layout bounds every plan
+    }
+    *plan = P;
+    return PIR_OK;
+}
 
-    k_zero_words<<<(2 * L.Bp + 255) / 256, 256, 0, s>>>(reinterpret_cast<uint32_t*>(colsum),
-                                                         2 * L.Bp);
+// Zero the column sums, then write the limb planes and column sums of the
+// queries into `base` (the layout of `P`).
+static pir_status ingest(const pir_db_t* db, const BatchIO& io, uint32_t B, const BatchPlan& P,
+                  bool narrow, uint8_t* base, hipStream_t s) {
+    const uint32_t C = (uint32_t)db->cols;
+    int8_t* QL = reinterpret_cast<int8_t*>(base);
+    u64* colsum = reinterpret_cast<u64*>(base + P.colsum_off);
+    k_zero_words<<<(2 * P.Bp + 255) / 256, 256, 0, s>>>(reinterpret_cast<uint32_t*>(colsum),
+                                                         2 * P.Bp);
     PIR_LAUNCH_CHECK();
-    dim3 ig((L.Bp + kIngB - 1) / kIngB, L.Cp / kIngJ);
+    dim3 ig((P.Bp + kIngB - 1) / kIngB, P.Cp / kIngJ);
     const bool qmajor = io.q_ldj == 1;
     const bool vec = ((uintptr_t)io.Q % 16 == 0) &&
                      (qmajor ? (io.q_ldb % 4 == 0 && C % 4 == 0) : (io.q_ldj % 4 == 0 && B % 4 == 0));
 #define PIR_INGEST(QM, V)                                                                  \
-    k_ingest<QM, V><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, L.Bp, L.Cp, QL, colsum, \
-                                       vi.narrow)
+    k_ingest<QM, V><<<ig, 256, 0, s>>>(io.Q, io.q_ldj, io.q_ldb, C, B, P.Bp, P.Cp, QL, colsum, \
+                                       narrow)
     if (qmajor) {
         if (vec) PIR_INGEST(true, true); else PIR_INGEST(true, false);
     } else {
@@ -1333,32 +1374,82 @@ pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
     }
 #undef PIR_INGEST
     PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
 
-    const uint32_t M = rows ? m : (uint32_t)db->rows;
-    if (M == 0) return PIR_OK;
-    const SplitPlan sp = plan_splits(M, L.N, C, vi, exact);
-    if (sp.splits > 1 && L.part_off + (size_t)sp.splits * M * B * 8 > L.total)
-        return PIR_ERR_WORKSPACE;   // cannot happen: the layout bounds every plan
+// Enqueue a planned batched call; `ws` holds at least plan.need bytes.  With
+// `planes` (the wide-layout limb planes and column sums of these queries,
+// written by mfma_ingest_planes) the ingest is skipped.
+pir_status mfma_run_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
+                          const uint32_t* rows, uint32_t modulus, const BatchPlan& P, void* ws,
+                          const void* planes, hipStream_t s) {
+    if (P.few) return few_answer_batch(db, io, B, modulus, ws, P.need, s);
+    const uint32_t C = (uint32_t)db->cols;
+    const bool exact = modulus != 0;
+    const VariantInfo& vi = kVariants[P.variant];
+    uint8_t* base = static_cast<uint8_t*>(ws);
+    const uint8_t* qbase = planes ? static_cast<const uint8_t*>(planes) : base;
+    const int8_t* QL = reinterpret_cast<const int8_t*>(qbase);
+    const u64* colsum = reinterpret_cast<const u64*>(qbase + P.colsum_off);
+    if (!planes) {
+        const pir_status st = ingest(db, io, B, P, vi.narrow, base, s);
+        if (st != PIR_OK) return st;
+    }
+    if (P.M == 0) return PIR_OK;
 
     Gemm g;
     g.db = db;
     g.QL = QL;
-    g.Cp = L.Cp;
-    g.N = L.N;
+    g.Cp = P.Cp;
+    g.N = P.N;
     g.exact = exact;
-    g.splits = sp.splits;
-    g.kts = sp.kts;
-    g.e = Epi{M,          B,       (uint32_t)db->rows, C, rows, colsum, db->rowsum, io.out,
-              io.o_ldr,   io.o_ldb, base + L.part_off, modulus};
+    g.splits = P.splits;
+    g.kts = P.kts;
+    g.e = Epi{P.M,      B,        (uint32_t)db->rows, C, rows, colsum, db->rowsum, io.out,
+              io.o_ldr, io.o_ldb, base + P.part_off, modulus};
     pir_status st = vi.launch(g, s);
-    if (st != PIR_OK || sp.splits <= 1) return st;
-    const uint64_t n = (uint64_t)M * B;
+    if (st != PIR_OK || P.splits <= 1) return st;
+    const uint64_t n = (uint64_t)P.M * B;
     if (n == 0) return PIR_OK;
-    if ((n + 255) / 256 > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
     if (exact)
-        k_finish<true><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, sp.splits);
+        k_finish<true><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, P.splits);
     else
-        k_finish<false><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, sp.splits);
+        k_finish<false><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, P.splits);
     PIR_LAUNCH_CHECK();
     return PIR_OK;
+}
+
+pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
+                             const uint32_t* rows, uint32_t m, uint32_t modulus, void* ws,
+                             size_t ws_bytes, const void* planes, size_t planes_bytes,
+                             hipStream_t s) {
+    BatchPlan plan;
+    const pir_status st = mfma_plan_batch(db, B, rows, m, modulus, planes != nullptr, &plan);
+    if (st != PIR_OK) return st;
+    // The reported size is the contract for every kernel path.
+    if (!ws || ws_bytes < mfma_workspace_bytes(db, B) || ((uintptr_t)ws % kWsAlign))
+        return PIR_ERR_WORKSPACE;
+    if (planes && (planes_bytes < mfma_planes_bytes(db, B) || ((uintptr_t)planes % kWsAlign)))
+        return PIR_ERR_WORKSPACE;
+    return mfma_run_batch(db, io, B, rows, modulus, plan, ws, planes, s);
+}
+
+size_t mfma_planes_bytes(const pir_db_t* db, uint32_t n) {
+    if (n == 0) return 0;
+    return batch_layout(db, n, kVariants[kVarRing128]).part_off;
+}
+
+pir_status mfma_ingest_planes(const pir_db_t* db, const uint32_t* A, uint32_t n, void* planes,
+                              size_t planes_bytes, hipStream_t s) {
+    BatchLayout L = batch_layout(db, n, kVariants[kVarRing128]);
+    if (!planes || planes_bytes < L.part_off || ((uintptr_t)planes % kWsAlign))
+        return PIR_ERR_WORKSPACE;
+    if ((uint64_t)L.Cp / kIngJ > g_max_grid_y) return PIR_ERR_SHAPE;
+    BatchPlan P{};
+    P.Bp = L.Bp;
+    P.N = L.N;
+    P.Cp = L.Cp;
+    P.colsum_off = L.colsum_off;
+    const BatchIO io{A, n, 1, nullptr, n, 1};
+    return ingest(db, io, n, P, false, static_cast<uint8_t*>(planes), s);
 }

@@ -38,7 +38,8 @@ const char* pir_status_string(pir_status status) {
         case PIR_ERR_SHAPE: return "shape out of range";
         case PIR_ERR_NO_MEMORY: return "out of memory";
         case PIR_ERR_DEVICE: return "device error";
-        case PIR_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
+        case PIR_ERR_UNSUPPORTED:
+            return "unsupported (gfx950 required, or no kernel serves this layout or variant)";
         case PIR_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
         case PIR_ERR_BUSY: return "queue full";
         case PIR_ERR_TIMEOUT: return "timed out";
@@ -46,7 +47,7 @@ const char* pir_status_string(pir_status status) {
     return "unknown status";
 }
 
-uint32_t pir_version(void) { return (1u << 16) | 0u; }
+uint32_t pir_version(void) { return (1u << 16) | 1u; }
 
 pir_status pir_db_open(uint8_t* d_D, uint64_t rows, uint64_t cols, uint64_t row_pitch,
                        pir_stream_t stream, pir_db_t** out) {
@@ -126,7 +127,7 @@ pir_status pir_answer_batch(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint3
     if (!d_Q || !d_out || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (B > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_Q, B, 1, d_out, B, 1};
-    return mfma_answer_batch(db, io, B, nullptr, 0, 0, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, B, nullptr, 0, 0, d_ws, ws_bytes, nullptr, 0,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -138,7 +139,7 @@ pir_status pir_answer_batch_qmajor(pir_db_t* db, const uint32_t* d_Qt, uint32_t 
     if (!d_Qt || !d_outT || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (B > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_Qt, 1, db->cols, d_outT, 1, db->rows};
-    return mfma_answer_batch(db, io, B, nullptr, 0, 0, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, B, nullptr, 0, 0, d_ws, ws_bytes, nullptr, 0,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -150,7 +151,7 @@ pir_status pir_answer_batch_modp(pir_db_t* db, const uint32_t* d_Q, uint32_t B, 
     if (!d_Q || !d_out || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (B > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_Q, B, 1, d_out, B, 1};
-    return mfma_answer_batch(db, io, B, nullptr, 0, p, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, B, nullptr, 0, p, d_ws, ws_bytes, nullptr, 0,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -159,7 +160,7 @@ pir_status pir_setup_hint(pir_db_t* db, const uint32_t* d_A, uint32_t n, uint32_
     if (!db_ok(db) || !d_A || !d_H || n == 0 || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
     if (n > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_A, n, 1, d_H, n, 1};
-    return mfma_answer_batch(db, io, n, nullptr, 0, 0, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, n, nullptr, 0, 0, d_ws, ws_bytes, nullptr, 0,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -184,7 +185,34 @@ pir_status pir_hint_update_rows(pir_db_t* db, const uint32_t* d_rows, uint32_t m
     if (m > db->rows) return PIR_ERR_SHAPE;
     if (n > kMaxBatch) return PIR_ERR_SHAPE;
     const BatchIO io{d_A, n, 1, d_H, n, 1};
-    return mfma_answer_batch(db, io, n, d_rows, m, 0, d_ws, ws_bytes,
+    return mfma_answer_batch(db, io, n, d_rows, m, 0, d_ws, ws_bytes, nullptr, 0,
+                             static_cast<hipStream_t>(stream));
+}
+
+size_t pir_hint_planes_bytes(const pir_db_t* db, uint32_t n) {
+    if (!db_ok(db) || n > kMaxBatch) return 0;
+    return mfma_planes_bytes(db, n);
+}
+
+pir_status pir_hint_planes(pir_db_t* db, const uint32_t* d_A, uint32_t n, void* d_planes,
+                           size_t planes_bytes, pir_stream_t stream) {
+    if (!db_ok(db) || !d_A || n == 0 || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
+    if (n > kMaxBatch) return PIR_ERR_SHAPE;
+    return mfma_ingest_planes(db, d_A, n, d_planes, planes_bytes,
+                              static_cast<hipStream_t>(stream));
+}
+
+pir_status pir_hint_update_rows_planes(pir_db_t* db, const uint32_t* d_rows, uint32_t m,
+                                       const void* d_planes, size_t planes_bytes, uint32_t n,
+                                       uint32_t* d_H, void* d_ws, size_t ws_bytes,
+                                       pir_stream_t stream) {
+    if (!db_ok(db)) return PIR_ERR_INVALID_ARG;
+    if (m == 0) return PIR_OK;
+    if (!d_rows || !d_planes || !d_H || n == 0 || !on_db_device(db)) return PIR_ERR_INVALID_ARG;
+    if (m > db->rows) return PIR_ERR_SHAPE;
+    if (n > kMaxBatch) return PIR_ERR_SHAPE;
+    const BatchIO io{nullptr, n, 1, d_H, n, 1};
+    return mfma_answer_batch(db, io, n, d_rows, m, 0, d_ws, ws_bytes, d_planes, planes_bytes,
                              static_cast<hipStream_t>(stream));
 }
 

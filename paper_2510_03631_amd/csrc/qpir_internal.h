@@ -86,10 +86,36 @@ uint32_t mfma_variant_count();
 const char* mfma_variant_name(uint32_t v);
 bool mfma_variant_valid(const pir_db_t* db, uint32_t B, uint32_t v, bool gathered);
 size_t mfma_workspace_bytes(const pir_db_t* db, uint32_t B);
+// A batched call's choices (variant, layout, split-K plan) and the
+// workspace bytes it touches, all checked before anything is enqueued.
+struct BatchPlan {
+    uint32_t variant;
+    bool few;                    // dot4 stream (answer_gemv.hip)
+    uint32_t Bp, N, Cp;          // queries in the limb layout, limb rows, padded columns
+    size_t colsum_off, part_off;
+    uint32_t M, splits, kts;     // output rows, split-K pieces, k-tiles per piece
+    size_t need;                 // workspace bytes the call touches
+};
 // modulus == 0: Out mod 2^32; otherwise Out mod modulus (field form).
+// Returns an error, with nothing enqueued, for calls the kernels cannot serve.
+// `planes`: the call will read pre-ingested wide-layout limb planes.
+pir_status mfma_plan_batch(const pir_db_t* db, uint32_t B, const uint32_t* rows, uint32_t m,
+                           uint32_t modulus, bool planes, BatchPlan* plan);
+// Enqueue a planned call; `ws` must hold plan.need bytes, 256-byte aligned;
+// `planes` (or null) as written by mfma_ingest_planes for these queries.
+pir_status mfma_run_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
+                          const uint32_t* rows, uint32_t modulus, const BatchPlan& plan, void* ws,
+                          const void* planes, hipStream_t s);
+// Plan, check the workspace against mfma_workspace_bytes (and the planes
+// against mfma_planes_bytes), run.
 pir_status mfma_answer_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
                              const uint32_t* rows, uint32_t m, uint32_t modulus, void* ws,
-                             size_t ws_bytes, hipStream_t s);
+                             size_t ws_bytes, const void* planes, size_t planes_bytes,
+                             hipStream_t s);
+// Limb planes and column sums of n query columns in the wide layout.
+size_t mfma_planes_bytes(const pir_db_t* db, uint32_t n);
+pir_status mfma_ingest_planes(const pir_db_t* db, const uint32_t* A, uint32_t n, void* planes,
+                              size_t planes_bytes, hipStream_t s);
 
 // ---- XOR (Chor) path (chor.hip)
 bool current_is_gfx950();

@@ -123,6 +123,7 @@ struct pir_server {
     bool started = false, stopping = false;
     pir_status fault = PIR_OK;
     uint64_t used = 0, peak = 0;
+    uint64_t alloc_bytes = 0;           // device memory of the slots (buffers, workspaces)
     uint64_t n_batches = 0, n_batched = 0, n_done = 0, n_failed = 0, n_rejected = 0;
     uint32_t n_computing = 0;           // batches whose kernels have not finished
 
@@ -203,6 +204,7 @@ struct pir_server {
             hipMalloc((void**)&s.d_O, (size_t)mb * d.R * 4) != hipSuccess ||
             (s.ws_bytes && hipMalloc(&s.d_ws, s.ws_bytes) != hipSuccess))
             return PIR_ERR_NO_MEMORY;
+        alloc_bytes += (uint64_t)mb * (d.C + d.R) * 4 + s.ws_bytes;
         if (hipMemset(s.d_Q, 0, (size_t)mb * d.C * 4) != hipSuccess) return PIR_ERR_DEVICE;
         const uint32_t nb = log2_floor(mb) + 1;
         s.graph.assign(nb, nullptr);
@@ -524,7 +526,15 @@ pir_status pir_server_wait(pir_server_t* s, uint64_t ticket, uint64_t timeout_ns
 pir_status pir_server_drain(pir_server_t* s) {
     if (!s) return PIR_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] { return s->n_done + s->n_failed >= s->reqs.size(); });
+    // Requests held by a paused database finish only after its resume, so
+    // waiting for them here would block until another thread resumes it.
+    auto held = [&] {
+        for (auto& d : s->dbs)
+            if (d.paused && !d.queue.empty()) return true;
+        return false;
+    };
+    s->cv_done.wait(lk, [&] { return s->n_done + s->n_failed >= s->reqs.size() || held(); });
+    if (s->n_done + s->n_failed < s->reqs.size()) return PIR_ERR_BUSY;
     return s->n_failed ? PIR_ERR_DEVICE : PIR_OK;
 }
 
@@ -534,6 +544,7 @@ pir_status pir_server_pause_db(pir_server_t* s, uint32_t db_index) {
     if (db_index >= s->dbs.size()) return PIR_ERR_INVALID_ARG;
     DbQueue& d = s->dbs[db_index];
     d.paused = true;
+    s->cv_done.notify_all();   // a drain in progress stops waiting on this queue
     s->cv_done.wait(lk, [&] { return d.inflight == 0; });
     return PIR_OK;
 }
@@ -544,6 +555,7 @@ pir_status pir_server_resume_db(pir_server_t* s, uint32_t db_index) {
     if (db_index >= s->dbs.size()) return PIR_ERR_INVALID_ARG;
     s->dbs[db_index].paused = false;
     s->cv_sched.notify_all();
+    s->cv_done.notify_all();
     return PIR_OK;
 }
 
@@ -561,6 +573,7 @@ pir_status pir_server_stats_get(pir_server_t* s, pir_server_stats* out) {
         out->batched_queries = s->n_batched;
         out->budget_bytes = s->cfg.mem_budget_bytes;
         out->peak_inflight_bytes = s->peak;
+        out->device_bytes = s->alloc_bytes;
         lat.reserve(s->n_done);
         for (auto& r : s->reqs)
             if (r.state.load(std::memory_order_acquire) == kDone) lat.push_back(r.t_done - r.t_arrival);
@@ -619,6 +632,7 @@ pir_status pir_server_destroy(pir_server_t* s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stopping = true;
+        for (auto& d : s->dbs) d.paused = false;   // held requests finish too
         s->cv_sched.notify_all();
     }
     if (s->sched.joinable()) s->sched.join();

@@ -243,3 +243,32 @@ def test_narrow_variants_in_graphs(env):
     for (rep, d, i), out in outs.items():
         assert np.array_equal(out, expected[d][i]), (rep, d, i)
     assert st["failed"] == 0 and st["batches"] < st["completed"]
+
+
+def test_paused_queue_drain_and_destroy(env):
+    """A drain while a paused database holds queued requests returns BUSY
+    instead of blocking; destroying the server resumes the database and
+    finishes them (answers equal the oracle's)."""
+    from paper_2510_03631_amd.serve import Server
+    qp = env["qp"]
+    banner("server: drain while paused, destroy finishes held requests")
+    dbs, queries, expected = env["dbs"], env["queries"], env["expected"]
+    srv = Server(dbs, max_batch=16, slots_per_db=2)
+    try:
+        srv.pause(1)
+        outs = []
+        for i in range(5):
+            outs.append(np.zeros(SHAPES[1][0], dtype=np.uint32))
+            srv.submit(1, queries[1][i], outs[-1])
+        other = np.zeros(SHAPES[0][0], dtype=np.uint32)
+        srv.wait(srv.submit(0, queries[0][0], other))   # other databases keep serving
+        with pytest.raises(qp.PirError) as e:
+            srv.drain()
+        assert e.value.status == 7
+        st = srv.stats()
+        assert st["completed"] == 1 and st["device_bytes"] > 0
+    finally:
+        srv.close()   # resumes database 1 and finishes its five requests
+    assert np.array_equal(other, expected[0][0])
+    for i in range(5):
+        assert np.array_equal(outs[i], expected[1][i]), i

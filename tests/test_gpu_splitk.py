@@ -95,3 +95,55 @@ def test_workspace_covers_every_plan(qp):
             H = torch.zeros((R, B), dtype=torch.int32, device="cuda")
             db.hint_update_rows(to_dev_u32(rows), to_dev_u32(Q), H, ws=ws)
             assert np.array_equal(to_host_u32(H)[rows], oracle.hint(D, Q, rows=rows))
+
+
+@pytest.mark.parametrize("m,n,C", [(37, 256, 16384), (300, 1024, 8192 + 48), (1, 5, 4096),
+                                   (129, 64, 2064)])
+def test_incremental_hint_prepared_planes(qp, m, n, C):
+    """A's limb planes prepared once (pir_hint_planes), then two refreshes
+    in a row whose incremental hints read them: each equals the oracle's
+    hint of the refreshed rows and the call that re-derives the planes from
+    A, for every variant of the gathered table (narrow ones fall back to the
+    wide layout the planes use)."""
+    import torch
+    R = 2048
+    g = np.random.default_rng(1000 + m + n)
+    D = g.integers(0, 256, size=(R, C), dtype=np.uint8)
+    A = workload.uniform_u32(g, (C, n))
+    with qp.Database(to_dev_u8(D)) as db:
+        Ad = to_dev_u32(A)
+        planes = db.hint_planes(Ad)
+        assert planes.numel() == qp.lib().pir_hint_planes_bytes(db.handle, n)
+        H_pl = torch.zeros((R, n), dtype=torch.int32, device="cuda")
+        H_a = torch.zeros((R, n), dtype=torch.int32, device="cuda")
+        for rep in range(2):
+            rows = workload.distinct_rows(g, R, m)
+            new = g.integers(0, 256, size=(m, C), dtype=np.uint8)
+            D = oracle.update_rows(D, rows, new)
+            exp = oracle.hint(D, A, rows=rows)
+            rows_d = to_dev_u32(rows)
+            db.update_rows(rows_d, to_dev_u8(new))
+            for v, name in [(0, "auto")] + _ring_variants(qp, n):
+                try:
+                    db.set_variant(n, v, rows=True)
+                except qp.PirError:
+                    continue
+                banner(f"prepared planes m={m} n={n} C={C} rep={rep} {name}")
+                db.hint_update_rows_planes(rows_d, planes, n, H_pl)
+                db.hint_update_rows(rows_d, Ad, H_a)
+                got = to_host_u32(H_pl)
+                assert np.array_equal(got[rows], exp), name
+                assert np.array_equal(got, to_host_u32(H_a)), name
+        db.set_variant(n, 0, rows=True)
+        # planes too small or missing: rejected, nothing written
+        lib = qp.lib()
+        ws = db.workspace(n)
+        before = to_host_u32(H_pl)
+        assert lib.pir_hint_update_rows_planes(db.handle, rows_d.data_ptr(), m, planes.data_ptr(),
+                                               planes.numel() - 1, n, H_pl.data_ptr(),
+                                               ws.data_ptr(), ws.numel(), None) == 6
+        assert lib.pir_hint_update_rows_planes(db.handle, rows_d.data_ptr(), m, None, 0, n,
+                                               H_pl.data_ptr(), ws.data_ptr(), ws.numel(),
+                                               None) == 1
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host_u32(H_pl), before)
