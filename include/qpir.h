@@ -141,6 +141,32 @@ pir_status pir_answer_batch(pir_db_t* db, const uint32_t* d_Q, uint32_t B, uint3
                             void* d_ws, size_t ws_bytes, pir_stream_t stream);
 
 /*
+ * Allocation-free batched Answer, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operands, kernels and results as
+ * pir_answer_batch (column b bit-identical to pir_answer on Q[:, b]), but
+ * without a workspace argument: the limb planes, column sums and split-K
+ * partials go to a fixed array of PIR_NOALLOC_SCRATCH_BYTES of device
+ * memory that the library holds on each device it runs on until the
+ * process ends.  The call allocates nothing.
+ *
+ *   d_Q    C x B words, row-major.   d_out  R x B words, row-major.
+ *
+ * Every call on one device shares that device's array: calls that overlap
+ * on a device (other streams, other threads, other handles) race and give
+ * undefined results; the caller orders them (one stream, or events).  The
+ * array keeps the last call's contents; each call rewrites what it reads.
+ * Errors: as pir_answer_batch, and PIR_ERR_SHAPE (nothing enqueued) when
+ * the call needs more than PIR_NOALLOC_SCRATCH_BYTES of scratch (about
+ * 4 * B * C bytes of limb planes plus the split-K partials; 64 queries fit
+ * a 32768 x 32768 database), PIR_ERR_DEVICE when the array's address could
+ * not be resolved on this device.
+ */
+#define PIR_NOALLOC_SCRATCH_BYTES (64u << 20)
+pir_status pir_answer_batch_noalloc(pir_db_t* db, const uint32_t* d_Q, uint32_t B,
+                                    uint32_t* d_out, pir_stream_t stream);
+
+/*
  * Batched Answer in query-major layout: query b is the contiguous row
  * Qt[b][0..C) and its answer the contiguous row outT[b][0..R), i.e.
  * outT[b][r] = sum_j D[r][j] * Qt[b][j] mod 2^32.  Same kernels and results

@@ -61,6 +61,7 @@ SIGNATURES = {
     "pir_hint_update_rows": (_ST, [_P, _P, _U32, _P, _U32, _P, _P, _SZ, _P]),
     "pir_answer_batch_qmajor": (_ST, [_P, _P, _U32, _P, _P, _SZ, _P]),
     "pir_answer_batch_modp": (_ST, [_P, _P, _U32, _U32, _P, _P, _SZ, _P]),
+    "pir_answer_batch_noalloc": (_ST, [_P, _P, _U32, _P, _P]),
     "pir_hint_planes_bytes": (_SZ, [_P, _U32]),
     "pir_hint_planes": (_ST, [_P, _P, _U32, _P, _SZ, _P]),
     "pir_hint_update_rows_planes": (_ST, [_P, _P, _U32, _P, _SZ, _U32, _P, _P, _SZ, _P]),
@@ -254,6 +255,19 @@ class Database:
         wp, wn = self._ws_args(ws)
         check(lib().pir_answer_batch(self.handle, qp, B, op, wp, wn,
                                      _stream_ptr(stream, self.device)), "pir_answer_batch")
+        return out
+
+    def answer_batch_noalloc(self, Q: torch.Tensor, out: torch.Tensor, stream=None):
+        """``pir_answer_batch`` without a workspace or any allocation
+        (``pir_answer_batch_noalloc``): the caller passes ``out`` (R x B)."""
+        if Q.dim() != 2:
+            raise ValueError("Q must be C x B")
+        B = int(Q.shape[1])
+        qp = _ptr_words(Q, "Q", (self.cols, B), self.device)
+        op = _ptr_words(out, "out", (self.rows, B), self.device)
+        check(lib().pir_answer_batch_noalloc(self.handle, qp, B, op,
+                                             _stream_ptr(stream, self.device)),
+              "pir_answer_batch_noalloc")
         return out
 
     def answer_batch_qmajor(self, Qt: torch.Tensor, out: torch.Tensor = None, stream=None,

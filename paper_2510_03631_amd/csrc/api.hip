@@ -58,6 +58,7 @@ pir_status pir_db_open(uint8_t* d_D, uint64_t rows, uint64_t cols, uint64_t row_
     if (hipGetDevice(&dev) != hipSuccess) return PIR_ERR_DEVICE;
     if (!device_is_gfx950(dev)) return PIR_ERR_UNSUPPORTED;
     if (init_once() != PIR_OK) return PIR_ERR_DEVICE;
+    (void)noalloc_init_device(dev);   // its outcome matters only to pir_answer_batch_noalloc
 
     pir_db_t* db = new (std::nothrow) pir_db_t();
     if (!db) return PIR_ERR_NO_MEMORY;

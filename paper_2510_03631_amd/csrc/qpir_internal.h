@@ -117,6 +117,11 @@ size_t mfma_planes_bytes(const pir_db_t* db, uint32_t n);
 pir_status mfma_ingest_planes(const pir_db_t* db, const uint32_t* A, uint32_t n, void* planes,
                               size_t planes_bytes, hipStream_t s);
 
+// ---- allocation-free batched Answer (noalloc.hip)
+// Resolve the device address of the fixed scratch array on `dev` (current),
+// once per device; later calls return the first outcome.
+pir_status noalloc_init_device(int dev);
+
 // ---- XOR (Chor) path (chor.hip)
 bool current_is_gfx950();
 // out[i] = init[i] (or 0) for i < n (a fill kernel: safe under graph capture).
