@@ -118,3 +118,30 @@ def test_unaligned_database_rejects_ring_variants(qp):
             db.set_variant(64, "ring_128x256_s6")
         db.set_variant(64, "reg_128x256")
         assert qp.variant_names(64)[db.get_variant(64)] == "reg_128x256"
+
+
+def test_wide_variants_accumulator_wrap(qp):
+    """Every variant that serves 64 queries, on the extremes at C = 131072:
+    centred products (-128)(-128) summed to 2^31 wrap the int32
+    accumulators; all-0xFF bytes against all-ones words; the answers equal
+    the closed form and the oracle."""
+    from paper_2510_03631_amd._lib import variant_names
+    R, C, B = 300, 131072, 64
+    cases = [(0, 0), (255, 0xFFFFFFFF), (0, 0x80808080), (255, 0x7F7F7F7F)]
+    tried = set()
+    for dval, qval in cases:
+        D = np.full((R, C), dval, dtype=np.uint8)
+        Q = np.full((C, B), qval, dtype=np.uint32)
+        exp = oracle.answer_batch(D, Q)
+        assert (exp == (dval * qval * C) % M32).all()
+        with qp.Database(to_dev_u8(D)) as db:
+            Qd = to_dev_u32(Q)
+            for v, name in enumerate(variant_names(B)):
+                try:
+                    db.set_variant(B, v)
+                except qp.PirError:
+                    continue
+                banner(f"wrap C={C} d={dval} q={qval:#x} {name}")
+                assert np.array_equal(to_host_u32(db.answer_batch(Qd)), exp), (name, dval, qval)
+                tried.add(name)
+    assert len(tried) >= 4
