@@ -265,6 +265,7 @@ def client_bench(stream) -> dict:
     gen = torch.Generator(device=dev)
     gen.manual_seed(workload.SEED_BASE + 62)
     res = {"workload": f"A {C} x {n} and H {R} x {n} uint32 words (128 MiB each)"}
+    Am, Hm = qp.ClientMatrix(A), qp.ClientMatrix(H)   # byte planes for the matrix cores
     for B in (1, 4, 16, 64):
         S = workload.device_u32((B, n), workload.SEED_BASE + 63 + B, dev)
         E = torch.randint(-40, 41, (B, C), dtype=torch.int32, device=dev, generator=gen)
@@ -287,6 +288,25 @@ def client_bench(stream) -> dict:
                         "decode_us": round(td * 1e6, 1), "decode_gbs": round(bd / td / 1e9, 1),
                         "decode_hbm_frac": round(bd / td / 1e9 / HBM_PEAK_GBS, 4),
                         "macs_per_s": round(C * n * B / tq, 1)}
+        if B >= 16:
+            # The same steps on the matrix cores (byte planes prepared once).
+            wsq = Am.workspace(B)
+            wsd = Hm.workspace(B)
+            fqm = lambda: Am.query(S, E, cols, out=Qt, ws=wsq)
+            fdm = lambda: Hm.decode(S, ans, out=m, ws=wsd)
+            fqm()
+            fdm()
+            _, tqm = time_on_stream(fqm, 10, stream)
+            _, tdm = time_on_stream(fdm, 10, stream)
+            tqm /= 10
+            tdm /= 10
+            res[f"B{B}"].update({
+                "query_mfma_us": round(tqm * 1e6, 1), "decode_mfma_us": round(tdm * 1e6, 1),
+                # 10 of the 16 limb-pair products matter mod 2^32; the MFMA
+                # fraction counts the 16 the product computes
+                "query_mfma_frac": round(8.0 * C * 4 * n * B / tqm / 1e12 / INT8_PEAK_TOPS, 4)})
+    Am.close()
+    Hm.close()
     del A, H
     torch.cuda.empty_cache()
     return res

@@ -296,6 +296,43 @@ pir_status pir_client_decode(const uint32_t* d_H, uint32_t R, uint32_t n, const 
                              pir_stream_t stream);
 
 /*
+ * The same client steps on the matrix cores, for batches of secrets.  Over
+ * Z/2^32 a word matrix is the sum of its byte planes, M = sum_i 2^(8i) M_i,
+ * so M x = [M_0 | M_1 | M_2 | M_3] [x; 2^8 x; 2^16 x; 2^24 x]: a byte matrix
+ * times a word vector, the Answer product itself.  A prepared client matrix
+ * holds those byte planes (the public matrix A for queries, the hint H for
+ * decoding) and a batch of B secrets runs through the batched Answer, then
+ * the query or decode epilogue.  Results are bit-identical to
+ * pir_client_query / pir_client_decode.
+ *
+ * pir_client_mat_open: prepare M (rows x n words, row-major, device; read
+ *   during the call only).  Allocates rows x 4n bytes of device memory and a
+ *   database handle over them, owned by the returned object; synchronizes
+ *   `stream`.  Errors: PIR_ERR_INVALID_ARG, PIR_ERR_SHAPE,
+ *   PIR_ERR_UNSUPPORTED, PIR_ERR_NO_MEMORY, PIR_ERR_DEVICE.
+ * pir_client_mat_close: release it (synchronizes the device; NULL is a no-op).
+ * pir_client_mat_workspace_bytes: workspace of a batch of B secrets, for
+ *   either call (0 for a bad handle or B).
+ * pir_client_query_mat: pir_client_query with A prepared: S, E, cols and Qt
+ *   as there, C = rows.
+ * pir_client_decode_mat: pir_client_decode with H prepared: S, answers and
+ *   out as there, R = rows.
+ *   d_ws  workspace of pir_client_mat_workspace_bytes(M, B) bytes, 256-byte
+ *         aligned (PIR_ERR_WORKSPACE otherwise).
+ */
+typedef struct pir_client_mat pir_client_mat_t;
+pir_status pir_client_mat_open(const uint32_t* d_M, uint32_t rows, uint32_t n,
+                               pir_stream_t stream, pir_client_mat_t** out);
+pir_status pir_client_mat_close(pir_client_mat_t* mat);
+size_t pir_client_mat_workspace_bytes(const pir_client_mat_t* mat, uint32_t B);
+pir_status pir_client_query_mat(pir_client_mat_t* A, const uint32_t* d_S, const int32_t* d_E,
+                                const uint32_t* d_cols, uint32_t B, uint32_t* d_Qt, void* d_ws,
+                                size_t ws_bytes, pir_stream_t stream);
+pir_status pir_client_decode_mat(pir_client_mat_t* H, const uint32_t* d_S,
+                                 const uint32_t* d_answers, uint32_t B, uint8_t* d_out,
+                                 void* d_ws, size_t ws_bytes, pir_stream_t stream);
+
+/*
  * Chor XOR PIR response (the ENS instantiation, Section 5.1; the server step
  * of Algorithm 3), for B queries:
  *     out[b] = XOR of the rows i of DB whose bit i is set in query b.

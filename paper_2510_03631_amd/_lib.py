@@ -84,6 +84,11 @@ SIGNATURES = {
     "pir_server_destroy": (_ST, [_P]),
     "pir_client_query": (_ST, [_P, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
     "pir_client_decode": (_ST, [_P, _U32, _U32, _P, _P, _U32, _P, _P]),
+    "pir_client_mat_open": (_ST, [_P, _U32, _U32, _P, ctypes.POINTER(_P)]),
+    "pir_client_mat_close": (_ST, [_P]),
+    "pir_client_mat_workspace_bytes": (_SZ, [_P, _U32]),
+    "pir_client_query_mat": (_ST, [_P, _P, _P, _P, _U32, _P, _P, _SZ, _P]),
+    "pir_client_decode_mat": (_ST, [_P, _P, _P, _U32, _P, _P, _SZ, _P]),
     "pir_chor_answer": (_ST, [_P, _U32, _U32, _U64, _P, _U32, _P, _P]),
     "pir_prg_expand": (_ST, [_P, _U32, _U32, _P, _P]),
     "pir_oop_workspace_bytes": (_SZ, [_U32, _U32, _U32]),
@@ -440,6 +445,82 @@ def client_decode(H: torch.Tensor, S: torch.Tensor, answers: torch.Tensor,
         check(lib().pir_client_decode(hp, R, n, sp, ap, B, op, _stream_ptr(stream, dev)),
               "pir_client_decode")
     return out
+
+
+class ClientMatrix:
+    """A word matrix prepared for the matrix-core client steps
+    (``pir_client_mat_*``): the public matrix A for :meth:`query`, the hint H
+    for :meth:`decode`.  Holds rows x 4n bytes of device memory until
+    :meth:`close`."""
+
+    def __init__(self, M: torch.Tensor, stream=None):
+        if M.dim() != 2:
+            raise ValueError("M must be rows x n")
+        self.rows, self.n = int(M.shape[0]), int(M.shape[1])
+        self.device = M.device
+        mp = _ptr_words(M, "M", (self.rows, self.n), self.device)
+        h = _P()
+        with torch.cuda.device(self.device):
+            check(lib().pir_client_mat_open(mp, self.rows, self.n,
+                                            _stream_ptr(stream, self.device), ctypes.byref(h)),
+                  "pir_client_mat_open")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            h, self._h = self._h, None
+            check(lib().pir_client_mat_close(h), "pir_client_mat_close")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def workspace(self, B: int) -> torch.Tensor:
+        nb = int(lib().pir_client_mat_workspace_bytes(self._h, B))
+        return torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+
+    def query(self, S: torch.Tensor, E: torch.Tensor, cols: torch.Tensor,
+              out: torch.Tensor = None, ws: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """``Qt[b] = A S[b] + E[b] + 2^24 u_{cols[b]}`` (B x C words)."""
+        B = int(S.shape[0])
+        sp = _ptr_words(S, "S", (B, self.n), self.device)
+        ep = _ptr_words(E, "E", (B, self.rows), self.device)
+        cp = _ptr_words(cols, "cols", (B,), self.device)
+        if out is None:
+            out = torch.empty((B, self.rows), dtype=torch.int32, device=self.device)
+        op = _ptr_words(out, "out", (B, self.rows), self.device)
+        if ws is None:
+            ws = self.workspace(B)
+        with torch.cuda.device(self.device):
+            check(lib().pir_client_query_mat(self._h, sp, ep, cp, B, op, ws.data_ptr(),
+                                             ws.numel(), _stream_ptr(stream, self.device)),
+                  "pir_client_query_mat")
+        return out
+
+    def decode(self, S: torch.Tensor, answers: torch.Tensor, out: torch.Tensor = None,
+               ws: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """``((answers[b] - H S[b] + 2^23) mod 2^32) >> 24`` (B x R bytes)."""
+        B = int(S.shape[0])
+        sp = _ptr_words(S, "S", (B, self.n), self.device)
+        ap = _ptr_words(answers, "answers", (B, self.rows), self.device)
+        if out is None:
+            out = torch.empty((B, self.rows), dtype=torch.uint8, device=self.device)
+        op = _ptr_bytes(out, "out", (B, self.rows), self.device)
+        if ws is None:
+            ws = self.workspace(B)
+        with torch.cuda.device(self.device):
+            check(lib().pir_client_decode_mat(self._h, sp, ap, B, op, ws.data_ptr(), ws.numel(),
+                                              _stream_ptr(stream, self.device)),
+                  "pir_client_decode_mat")
+        return out
 
 
 def chor_answer(DB: torch.Tensor, Q: torch.Tensor, out: torch.Tensor = None,

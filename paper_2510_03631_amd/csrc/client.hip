@@ -18,6 +18,8 @@
 // (b, part) ends with output (b, row).
 #include <string.h>
 
+#include <new>
+
 #include "qpir_internal.h"
 
 namespace {
@@ -147,9 +149,206 @@ uint32_t grid_for(uint32_t rows, int rb) {
     return blocks < 16384 ? (uint32_t)blocks : 16384u;
 }
 
+// ---------------------------------------------------------------- matrix-core path
+// Over Z/2^32 a word matrix is the sum of its byte planes, M = sum_i 2^(8i)
+// M_i, so M x = [M_0 | M_1 | M_2 | M_3] [x; 2^8 x; 2^16 x; 2^24 x]: a byte
+// matrix of 4n columns times a word vector of 4n entries, which is exactly
+// the Answer product D q.  A prepared client matrix holds the byte planes
+// (rows x 4n bytes, the same size as M) under a database handle, and a batch
+// of secrets runs on the matrix-core batched Answer, followed by the query
+// or decode epilogue.
+
+constexpr uint32_t kClientMatMagic = 0x434D4154u;   // "CMAT"
+
+// planes[r][i n + k] = byte i of M[r][k]; one thread per word.
+__global__ void k_byte_planes(const uint32_t* __restrict__ M, uint64_t words, uint32_t n,
+                              uint8_t* __restrict__ planes) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= words) return;
+    const uint64_t r = idx / n, k = idx % n;
+    const uint32_t w = M[idx];
+    uint8_t* row = planes + r * 4u * n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) row[(uint64_t)i * n + k] = (uint8_t)(w >> (8 * i));
+}
+
+// Xs[b][i n + k] = X[b][k] << 8i (mod 2^32): the secrets against the planes.
+__global__ void k_scale_secrets(const uint32_t* __restrict__ X, uint32_t B, uint32_t n,
+                                uint32_t* __restrict__ Xs) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)B * n) return;
+    const uint64_t b = idx / n, k = idx % n;
+    const uint32_t x = X[idx];
+    uint32_t* dst = Xs + b * 4u * n + k;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dst[(uint64_t)i * n] = x << (8 * i);
+}
+
+// Query epilogue, in place on the product: Qt[b][j] += E[b][j] (+ Delta at
+// the queried column).
+__global__ void k_query_epilogue(uint32_t* __restrict__ Qt, uint32_t C, uint32_t B,
+                                 const int32_t* __restrict__ E, const uint32_t* __restrict__ cols) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)B * C) return;
+    const uint32_t b = (uint32_t)(idx / C), j = (uint32_t)(idx % C);
+    uint32_t q = Qt[idx] + (uint32_t)E[idx];
+    if (j == cols[b]) q += kDelta;
+    Qt[idx] = q;
+}
+
+// Decode epilogue: out[b][r] = ((ans[b][r] - Y[b][r] + Delta/2) mod 2^32) >> 24.
+__global__ void k_decode_epilogue(const uint32_t* __restrict__ Y, const uint32_t* __restrict__ ans,
+                                  uint64_t count, uint8_t* __restrict__ out) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    out[idx] = (uint8_t)((ans[idx] - Y[idx] + kHalfDelta) >> 24);
+}
+
+// One thread per element in 256-thread blocks: at most 2^31 - 1 blocks.
+constexpr uint64_t kMaxGridWords = 0x7FFFFFFFull * 256u;
+uint32_t grid1d(uint64_t n) { return (uint32_t)((n + 255) / 256); }
+
+}  // namespace
+
+struct pir_client_mat {
+    uint32_t magic;
+    uint32_t rows, n;
+    int device;
+    uint8_t* planes;   // rows x 4n bytes, owned
+    pir_db_t* db;      // handle over the planes
+};
+
+namespace {
+
+bool mat_ok(const pir_client_mat_t* m) { return m && m->magic == kClientMatMagic; }
+
+// Workspace layout of a batch of B: scaled secrets, the product (decode
+// only), then the batched Answer's own workspace.
+struct MatWs {
+    size_t xs_off, y_off, ans_off, total;
+};
+
+MatWs mat_ws(const pir_client_mat_t* m, uint32_t B, bool decode) {
+    MatWs w;
+    w.xs_off = 0;
+    w.y_off = round_up((size_t)B * 4u * m->n * 4u, kWsAlign);
+    w.ans_off = w.y_off + (decode ? round_up((size_t)B * m->rows * 4u, kWsAlign) : 0);
+    w.total = w.ans_off + pir_workspace_bytes(m->db, B);
+    return w;
+}
+
+// Y[b] = M X[b] for the B secrets into y (B x rows words).
+pir_status mat_product(pir_client_mat_t* m, const uint32_t* X, uint32_t B, uint32_t* y,
+                       uint8_t* ws, const MatWs& w, hipStream_t st) {
+    uint32_t* xs = reinterpret_cast<uint32_t*>(ws + w.xs_off);
+    k_scale_secrets<<<grid1d((uint64_t)B * m->n), 256, 0, st>>>(X, B, m->n, xs);
+    PIR_LAUNCH_CHECK();
+    return pir_answer_batch_qmajor(m->db, xs, B, y, ws + w.ans_off, w.total - w.ans_off, st);
+}
+
 }  // namespace
 
 extern "C" {
+
+pir_status pir_client_mat_open(const uint32_t* d_M, uint32_t rows, uint32_t n,
+                               pir_stream_t stream, pir_client_mat_t** out) {
+    if (!d_M || !out) return PIR_ERR_INVALID_ARG;
+    if (rows == 0 || n == 0 || rows > kMaxDim || (uint64_t)4 * n > kMaxDim ||
+        (uint64_t)rows * n > kMaxGridWords)
+        return PIR_ERR_SHAPE;
+    if (!current_is_gfx950()) return PIR_ERR_UNSUPPORTED;
+    pir_client_mat_t* m = new (std::nothrow) pir_client_mat_t();
+    if (!m) return PIR_ERR_NO_MEMORY;
+    m->rows = rows;
+    m->n = n;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return PIR_ERR_DEVICE;
+    }
+    const uint64_t bytes = (uint64_t)rows * 4u * n;
+    if (hipMalloc((void**)&m->planes, bytes) != hipSuccess) {
+        delete m;
+        return PIR_ERR_NO_MEMORY;
+    }
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t words = (uint64_t)rows * n;
+    k_byte_planes<<<grid1d(words), 256, 0, st>>>(d_M, words, n, m->planes);
+    pir_status s = hipGetLastError() == hipSuccess ? PIR_OK : PIR_ERR_DEVICE;
+    if (s == PIR_OK) s = pir_db_open(m->planes, rows, 4u * n, 4u * n, stream, &m->db);
+    if (s != PIR_OK) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(m->planes);
+        delete m;
+        return s;
+    }
+    m->magic = kClientMatMagic;
+    *out = m;
+    return PIR_OK;
+}
+
+pir_status pir_client_mat_close(pir_client_mat_t* m) {
+    if (!m) return PIR_OK;
+    if (!mat_ok(m)) return PIR_ERR_INVALID_ARG;
+    pir_status st = pir_db_close(m->db);   // synchronizes the device
+    if (hipFree(m->planes) != hipSuccess) st = PIR_ERR_DEVICE;
+    m->magic = 0;
+    delete m;
+    return st;
+}
+
+size_t pir_client_mat_workspace_bytes(const pir_client_mat_t* m, uint32_t B) {
+    if (!mat_ok(m) || B == 0 || B > kMaxBatch) return 0;
+    return mat_ws(m, B, true).total;
+}
+
+pir_status pir_client_query_mat(pir_client_mat_t* A, const uint32_t* d_S, const int32_t* d_E,
+                                const uint32_t* d_cols, uint32_t B, uint32_t* d_Qt, void* d_ws,
+                                size_t ws_bytes, pir_stream_t stream) {
+    if (!mat_ok(A) || !d_S || !d_E || !d_cols || !d_Qt) return PIR_ERR_INVALID_ARG;
+    if (B == 0 || B > kMaxBatch || (uint64_t)B * A->rows > kMaxGridWords ||
+        (uint64_t)B * A->n > kMaxGridWords)
+        return PIR_ERR_SHAPE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != A->device) return PIR_ERR_INVALID_ARG;
+    if (!d_ws || ws_bytes < pir_client_mat_workspace_bytes(A, B) || (uintptr_t)d_ws % kWsAlign)
+        return PIR_ERR_WORKSPACE;
+    const MatWs w = mat_ws(A, B, false);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchPlan plan;   // every check of the product before anything is enqueued
+    pir_status s = mfma_plan_batch(A->db, B, nullptr, 0, 0, false, &plan);
+    if (s != PIR_OK) return s;
+    s = mat_product(A, d_S, B, d_Qt, static_cast<uint8_t*>(d_ws), w, st);
+    if (s != PIR_OK) return s;
+    k_query_epilogue<<<grid1d((uint64_t)B * A->rows), 256, 0, st>>>(d_Qt, A->rows, B, d_E, d_cols);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
+
+pir_status pir_client_decode_mat(pir_client_mat_t* H, const uint32_t* d_S,
+                                 const uint32_t* d_answers, uint32_t B, uint8_t* d_out,
+                                 void* d_ws, size_t ws_bytes, pir_stream_t stream) {
+    if (!mat_ok(H) || !d_S || !d_answers || !d_out) return PIR_ERR_INVALID_ARG;
+    if (B == 0 || B > kMaxBatch || (uint64_t)B * H->rows > kMaxGridWords ||
+        (uint64_t)B * H->n > kMaxGridWords)
+        return PIR_ERR_SHAPE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != H->device) return PIR_ERR_INVALID_ARG;
+    if (!d_ws || ws_bytes < pir_client_mat_workspace_bytes(H, B) || (uintptr_t)d_ws % kWsAlign)
+        return PIR_ERR_WORKSPACE;
+    const MatWs w = mat_ws(H, B, true);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchPlan plan;
+    pir_status s = mfma_plan_batch(H->db, B, nullptr, 0, 0, false, &plan);
+    if (s != PIR_OK) return s;
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    uint32_t* y = reinterpret_cast<uint32_t*>(ws + w.y_off);
+    s = mat_product(H, d_S, B, y, ws, w, st);
+    if (s != PIR_OK) return s;
+    const uint64_t count = (uint64_t)B * H->rows;
+    k_decode_epilogue<<<grid1d(count), 256, 0, st>>>(y, d_answers, count, d_out);
+    PIR_LAUNCH_CHECK();
+    return PIR_OK;
+}
 
 pir_status pir_client_query(const uint32_t* d_A, uint32_t C, uint32_t n, const uint32_t* d_S,
                             const int32_t* d_E, const uint32_t* d_cols, uint32_t B,

@@ -102,3 +102,83 @@ def test_client_errors(qp):
     p = t.data_ptr()
     assert lib.pir_client_query(p, 0, 4, p, p, p, 1, p, None) == 2
     assert lib.pir_client_decode(p, 4, 4, p, p, 0, p, None) == 2
+
+
+@pytest.mark.parametrize("R,C,n,B", [(1024, 1024, 1024, 16), (333, 1000, 77, 17),
+                                     (2000, 300, 64, 40), (100, 512, 1030, 5),
+                                     (1001, 1023, 256, 64), (64, 2048, 12, 1)])
+def test_client_matrix_core_round_trip(qp, R, C, n, B):
+    """The matrix-core client steps (A and H as byte planes under the
+    batched Answer) against the oracle's client: every query word, every
+    decoded byte, and the word path's outputs bit for bit.  n = 77 and 1030
+    give 4n not a multiple of 16 (the register-staged kernels); a ragged
+    batch of 17 and 40 pads the limb layout."""
+    banner(f"client matrix cores R={R} C={C} n={n} B={B}")
+    g = workload.rng(7 * R + C + n + B)
+    D = workload.db_bytes(g, R, C)
+    A = workload.uniform_u32(g, (C, n))
+    dr = workload.lwe_draws(g, C, n, B)
+    Ad, Sd = to_dev_u32(A), to_dev_u32(dr.s)
+    Ed, cd = _dev_i32(dr.e), to_dev_u32(dr.col.astype(np.uint32))
+    with qp.ClientMatrix(Ad) as Am:
+        Qt = Am.query(Sd, Ed, cd)
+        Qt_h = to_host_u32(Qt)
+        for b in range(B):
+            assert np.array_equal(Qt_h[b], oracle.lwe_query(A, dr.s[b], dr.e[b], int(dr.col[b]))), b
+        assert np.array_equal(Qt_h, to_host_u32(qp.client_query(Ad, Sd, Ed, cd)))
+        Qt2 = to_host_u32(Am.query(Sd, Ed, cd))          # the same handle again
+        assert np.array_equal(Qt2, Qt_h)
+    with qp.Database(to_dev_u8(D)) as db:
+        H = db.setup_hint(Ad)
+        ans = db.answer_batch_qmajor(Qt) if B > 1 else db.answer(Qt[0]).view(1, R)
+    H_h, ans_h = to_host_u32(H), to_host_u32(ans)
+    with qp.ClientMatrix(H) as Hm:
+        m = Hm.decode(Sd, ans).cpu().numpy()
+    for b in range(B):
+        assert np.array_equal(m[b], oracle.lwe_decode(ans_h[b], H_h, dr.s[b])), b
+        assert np.array_equal(m[b], D[:, int(dr.col[b])]), b
+
+
+def test_client_matrix_core_full_size(qp):
+    """32768 x 1024 public matrix and hint-shaped matrix, 64 secrets: every
+    query word against the oracle; decode against the oracle's decode of
+    uniform answers (a decode is defined for any answer words)."""
+    banner("client matrix cores 32768x1024, B=64")
+    g = workload.rng(workload.SEED_BASE + 2)
+    C, n, B = 32768, 1024, 64
+    A = workload.uniform_u32(g, (C, n))
+    dr = workload.lwe_draws(g, C, n, B)
+    Sd = to_dev_u32(dr.s)
+    with qp.ClientMatrix(to_dev_u32(A)) as Am:
+        Qt = to_host_u32(Am.query(Sd, _dev_i32(dr.e), to_dev_u32(dr.col.astype(np.uint32))))
+    for b in range(0, B, 7):
+        assert np.array_equal(Qt[b], oracle.lwe_query(A, dr.s[b], dr.e[b], int(dr.col[b]))), b
+    ans = workload.uniform_u32(g, (B, C))
+    with qp.ClientMatrix(to_dev_u32(A)) as Hm:
+        m = Hm.decode(Sd, to_dev_u32(ans)).cpu().numpy()
+    for b in range(0, B, 9):
+        assert np.array_equal(m[b], oracle.lwe_decode(ans[b], A, dr.s[b])), b
+
+
+def test_client_matrix_core_errors(qp):
+    import torch
+    banner("client matrix cores: argument errors")
+    import ctypes
+    lib = qp.lib()
+    out = ctypes.c_void_p()
+    assert lib.pir_client_mat_open(None, 4, 4, None, ctypes.byref(out)) == 1
+    t = torch.zeros(64, dtype=torch.int32, device="cuda")
+    assert lib.pir_client_mat_open(t.data_ptr(), 0, 4, None, ctypes.byref(out)) == 2
+    assert lib.pir_client_mat_workspace_bytes(None, 4) == 0
+    with qp.ClientMatrix(t.view(16, 4)) as m:
+        S = torch.zeros((2, 4), dtype=torch.int32, device="cuda")
+        E = torch.zeros((2, 16), dtype=torch.int32, device="cuda")
+        cols = torch.zeros(2, dtype=torch.int32, device="cuda")
+        Qt = torch.full((2, 16), 5, dtype=torch.int32, device="cuda")
+        ws = m.workspace(2)
+        assert lib.pir_client_query_mat(m._h, S.data_ptr(), E.data_ptr(), cols.data_ptr(), 2,
+                                        Qt.data_ptr(), ws.data_ptr(), ws.numel() - 1, None) == 6
+        assert lib.pir_client_query_mat(m._h, S.data_ptr(), E.data_ptr(), cols.data_ptr(), 0,
+                                        Qt.data_ptr(), ws.data_ptr(), ws.numel(), None) == 2
+        torch.cuda.synchronize()
+        assert int((Qt != 5).sum().item()) == 0   # nothing written
