@@ -568,8 +568,10 @@ def profile_mode(args, dev, stream) -> int:
                           "copy_gbs_read_plus_write": round(2 * x.numel() * 4 / t / 1e9, 1)}))
         return 0
     if args.profile.startswith("client"):
-        # clientB: query generation then decode for B queries at C = R = 32768.
-        B = int(args.profile[len("client"):])
+        # clientB: query generation then decode for B queries at C = R = 32768;
+        # clientmatB: the same on the matrix cores (byte planes prepared once).
+        mat = args.profile.startswith("clientmat")
+        B = int(args.profile[len("clientmat" if mat else "client"):])
         A = workload.device_u32((C, n), workload.SEED_BASE + 60, dev)
         H = workload.device_u32((R, n), workload.SEED_BASE + 61, dev)
         S = workload.device_u32((B, n), workload.SEED_BASE + 63 + B, dev)
@@ -578,9 +580,17 @@ def profile_mode(args, dev, stream) -> int:
         Qt = torch.empty((B, C), dtype=torch.int32, device=dev)
         m = torch.empty((B, R), dtype=torch.uint8, device=dev)
 
-        def fn():
-            qp.client_query(A, S, E, cols, out=Qt)
-            qp.client_decode(H, S, Qt, out=m)
+        if mat:
+            Am, Hm = qp.ClientMatrix(A), qp.ClientMatrix(H)
+            wsq, wsd = Am.workspace(B), Hm.workspace(B)
+
+            def fn():
+                Am.query(S, E, cols, out=Qt, ws=wsq)
+                Hm.decode(S, Qt, out=m, ws=wsd)
+        else:
+            def fn():
+                qp.client_query(A, S, E, cols, out=Qt)
+                qp.client_decode(H, S, Qt, out=m)
         for _ in range(args.warmup):
             fn()
         wall, ev = time_on_stream(fn, args.steps, stream)
@@ -715,7 +725,8 @@ def main() -> int:
     ap.add_argument("--profile",
                     help="run only one kernel family (for rocprofv3 runs) and exit: answer, "
                          "batchB, hint, update (incremental hint, 16 GiB), update_planes (the same "
-                         "from prepared limb planes), calibrate, intmm, "
+                         "from prepared limb planes), calibrate, intmm, clientB / clientmatB "
+                         "(LWE client, word path / matrix cores), "
                          "or chorB / oopB / ftrB / clientB with B queries")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -305,7 +305,163 @@ __global__ __launch_bounds__(kThreads) void k_chor_shared(const uint32_t* __rest
     }
 }
 
-template <int G>
+// The same with 8-row steps, for groups of 32 queries per wave: two 16-entry
+// tables per step (rows 0-3 and rows 4-7 of the step), and each query adds
+// one entry of each, acc ^= t0 ^ t1, one three-input XOR per word for two
+// lookups.  Per lookup that is two XOR instructions instead of four, and one
+// barrier per 8 rows, against twice the table memory (64 KiB per workgroup,
+// double-buffered) and twice the rows in flight per step.  (Written with
+// the compiler's bitop3 builtin, the kernel needed 458 registers, one wave
+// per SIMD, and ran at half the speed; as inline assembly it keeps 234.)
+// a ^ b ^ c as one gfx950 three-input bit operation (truth table 0x96).
+__device__ inline uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+template <int G, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_chor_shared8(const uint32_t* __restrict__ DB,
+                                                           uint64_t pitch, uint32_t rows,
+                                                           uint32_t W,
+                                                           const uint32_t* __restrict__ Q,
+                                                           uint32_t qwords, uint32_t B,
+                                                           uint32_t slab_rows, uint32_t n_qg,
+                                                           uint32_t n_cs,
+                                                           uint32_t* __restrict__ out) {
+    __shared__ u32x4 s_tab[2][2][16][64];         // [buffer][table][entry][lane], 64 KiB
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t qg = bid % n_qg;
+    const uint32_t cs = (bid / n_qg) % n_cs;
+    const uint32_t slab = bid / (n_qg * n_cs);
+    const uint32_t r0 = slab * slab_rows;
+    const uint32_t r1 = min(rows, r0 + slab_rows);
+    const uint32_t w = cs * 256u + 4u * lane;
+    const bool active = w < W;
+    const uint32_t qbase = (qg * 4u + (uint32_t)wave) * G;
+    const uint32_t nq = qbase < B ? min((uint32_t)G, B - qbase) : 0u;
+
+    if (wave < 2) {
+        s_tab[wave][0][0][lane] = u32x4{0, 0, 0, 0};
+        s_tab[wave][1][0][lane] = u32x4{0, 0, 0, 0};
+    }
+    u32x4 acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = u32x4{0, 0, 0, 0};
+
+    // Rows of each 4-row half this wave needs for its entries: 0 and 1
+    // always; 2 for waves 1 and 3; 3 for waves 2 and 3.
+    const bool need2 = wave == 1 || wave == 3;
+    const bool need3 = wave >= 2;
+    auto load_row = [&](uint32_t r) -> u32x4 {
+        return (active && r < r1) ? load_words_nt<VEC>(DB + (uint64_t)r * pitch, w, W)
+                                  : u32x4{0, 0, 0, 0};
+    };
+    auto load_step = [&](uint32_t st, u32x4 (&x)[8]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t r = r0 + 8u * st + 4u * h;
+            x[4 * h + 0] = load_row(r);
+            x[4 * h + 1] = load_row(r + 1);
+            x[4 * h + 2] = need2 ? load_row(r + 2) : u32x4{0, 0, 0, 0};
+            x[4 * h + 3] = need3 ? load_row(r + 3) : u32x4{0, 0, 0, 0};
+        }
+    };
+    // Selector words of the wave's G queries for one 32-row block (scalar
+    // loads for G <= 16, one lane per query above; see k_chor_shared).
+    constexpr bool kScalarSel = G <= 16;
+    auto load_sel = [&](uint32_t blk, uint32_t (&sel)[G]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t b = min(qbase + (uint32_t)g, B - 1u);
+            sel[g] = 32u * blk < rows ? Q[(uint64_t)b * qwords + blk] : 0u;
+        }
+    };
+    auto load_sel_lane = [&](uint32_t blk) -> uint32_t {
+        const uint32_t b = qbase + (uint32_t)lane;
+        return ((uint32_t)lane < nq && 32u * blk < rows) ? Q[(uint64_t)b * qwords + blk] : 0u;
+    };
+
+    const uint32_t nsteps = r1 > r0 ? (r1 - r0 + 7u) / 8u : 0u;
+    u32x4 xa[8], xb[8];
+    load_step(0, xa);
+    load_step(1, xb);
+    uint32_t qv[kScalarSel ? G : 1];
+    uint32_t qlane = 0, qlane_next = kScalarSel ? 0u : load_sel_lane(r0 / 32u);
+
+    auto step = [&](uint32_t st, u32x4 (&x)[8]) {
+        const int buf = st & 1;
+        if (st % 4u == 0) {
+            if constexpr (kScalarSel) {
+                load_sel(r0 / 32u + st / 4u, qv);
+            } else {
+                qlane = qlane_next;
+                qlane_next = load_sel_lane(r0 / 32u + st / 4u + 1u);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const u32x4 lo1 = x[4 * h], lo2 = x[4 * h + 1], lo3 = lo1 ^ lo2;
+            const u32x4 hi = wave == 0 ? u32x4{0, 0, 0, 0}
+                                       : (wave == 1 ? x[4 * h + 2]
+                                                    : (wave == 2 ? x[4 * h + 3]
+                                                                 : x[4 * h + 2] ^ x[4 * h + 3]));
+            if (wave != 0) s_tab[buf][h][4 * wave][lane] = hi;
+            s_tab[buf][h][4 * wave + 1][lane] = hi ^ lo1;
+            s_tab[buf][h][4 * wave + 2][lane] = hi ^ lo2;
+            s_tab[buf][h][4 * wave + 3][lane] = hi ^ lo3;
+        }
+        if (st + 2u < nsteps) load_step(st + 2u, x);    // prefetch two steps ahead
+        lds_barrier();
+        const int sh = 8 * (int)(st % 4u);
+        // Lookups in groups of KG queries (4 for 32 queries per wave, which
+        // keeps the kernel within 256 registers: two waves per SIMD).
+        constexpr int KG = G >= 32 ? 4 : 8;
+#pragma unroll
+        for (int g0 = 0; g0 < G; g0 += KG) {
+            u32x4 t0[KG], t1[KG];
+#pragma unroll
+            for (int g = 0; g < KG && g0 + g < G; ++g) {
+                const uint32_t word = kScalarSel ? qv[kScalarSel ? g0 + g : 0]
+                                                 : __builtin_amdgcn_readlane(qlane, g0 + g);
+                t0[g] = s_tab[buf][0][(word >> sh) & 15u][lane];
+                t1[g] = s_tab[buf][1][(word >> (sh + 4)) & 15u][lane];
+            }
+#pragma unroll
+            for (int g = 0; g < KG && g0 + g < G; ++g) {
+                u32x4& a = acc[g0 + g];   // a ^ t0 ^ t1 in one instruction per word
+                a.x = xor3(a.x, t0[g].x, t1[g].x);
+                a.y = xor3(a.y, t0[g].y, t1[g].y);
+                a.z = xor3(a.z, t0[g].z, t1[g].z);
+                a.w = xor3(a.w, t0[g].w, t1[g].w);
+            }
+            // Keep the groups apart: hoisting every group's reads would hold
+            // them all in registers at once.
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    for (uint32_t st = 0; st < nsteps; st += 2) {
+        step(st, xa);
+        if (st + 1 < nsteps) step(st + 1, xb);
+    }
+
+    if (active) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if ((uint32_t)g < nq) {
+                uint32_t* o = out + (uint64_t)(qbase + g) * W + w;
+                if (acc[g].x) atomicXor(o, acc[g].x);
+                if (w + 1 < W && acc[g].y) atomicXor(o + 1, acc[g].y);
+                if (w + 2 < W && acc[g].z) atomicXor(o + 2, acc[g].z);
+                if (w + 3 < W && acc[g].w) atomicXor(o + 3, acc[g].w);
+            }
+        }
+    }
+}
+
+template <int G, bool EIGHT = false>
 pir_status launch_shared(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
                          const uint32_t* d_Q, uint32_t B, uint32_t* d_out, uint32_t target,
                          hipStream_t s) {
@@ -322,12 +478,20 @@ pir_status launch_shared(const uint32_t* d_DB, uint32_t rows, uint32_t words, ui
     const uint64_t blocks = n_slabs * per_slab;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
     const bool vec = ((uintptr_t)d_DB % 16 == 0) && (words % 4 == 0) && (pitch % 4 == 0);
-    if (vec)
+    if (EIGHT) {
+        if (vec)
+            k_chor_shared8<G, true><<<(uint32_t)blocks, kThreads, 0, s>>>(
+                d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
+        else
+            k_chor_shared8<G, false><<<(uint32_t)blocks, kThreads, 0, s>>>(
+                d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
+    } else if (vec) {
         k_chor_shared<G, true><<<(uint32_t)blocks, kThreads, 0, s>>>(
             d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
-    else
+    } else {
         k_chor_shared<G, false><<<(uint32_t)blocks, kThreads, 0, s>>>(
             d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
+    }
     PIR_LAUNCH_CHECK();
     return PIR_OK;
 }
@@ -392,7 +556,7 @@ pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_
     if (B <= 16) return launch_shared<4>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
     if (B <= 32) return launch_shared<8>(d_DB, rows, words, pitch, d_Q, B, d_out, 1024, s);
     if (B <= 256) return launch_shared<16>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
-    return launch_shared<32>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
+    return launch_shared<32, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
 }
 
 extern "C" {
