@@ -313,6 +313,8 @@ pir_status pir_client_decode(const uint32_t* d_H, uint32_t R, uint32_t n, const 
  * pir_client_mat_close: release it (synchronizes the device; NULL is a no-op).
  * pir_client_mat_workspace_bytes: workspace of a batch of B secrets, for
  *   either call (0 for a bad handle or B).
+ * The secrets' operand goes straight into the product's limb layout (one
+ * kernel), so a call is that kernel, the product and the epilogue.
  * pir_client_query_mat: pir_client_query with A prepared: S, E, cols and Qt
  *   as there, C = rows.
  * pir_client_decode_mat: pir_client_decode with H prepared: S, answers and
@@ -325,6 +327,9 @@ pir_status pir_client_mat_open(const uint32_t* d_M, uint32_t rows, uint32_t n,
                                pir_stream_t stream, pir_client_mat_t** out);
 pir_status pir_client_mat_close(pir_client_mat_t* mat);
 size_t pir_client_mat_workspace_bytes(const pir_client_mat_t* mat, uint32_t B);
+/* Kernel variant of the product for batches in B's bucket (as
+ * pir_db_set_variant; for the autotuner). */
+pir_status pir_client_mat_set_variant(pir_client_mat_t* mat, uint32_t batch, uint32_t variant);
 pir_status pir_client_query_mat(pir_client_mat_t* A, const uint32_t* d_S, const int32_t* d_E,
                                 const uint32_t* d_cols, uint32_t B, uint32_t* d_Qt, void* d_ws,
                                 size_t ws_bytes, pir_stream_t stream);

@@ -87,6 +87,7 @@ SIGNATURES = {
     "pir_client_mat_open": (_ST, [_P, _U32, _U32, _P, ctypes.POINTER(_P)]),
     "pir_client_mat_close": (_ST, [_P]),
     "pir_client_mat_workspace_bytes": (_SZ, [_P, _U32]),
+    "pir_client_mat_set_variant": (_ST, [_P, _U32, _U32]),
     "pir_client_query_mat": (_ST, [_P, _P, _P, _P, _U32, _P, _P, _SZ, _P]),
     "pir_client_decode_mat": (_ST, [_P, _P, _P, _U32, _P, _P, _SZ, _P]),
     "pir_chor_answer": (_ST, [_P, _U32, _U32, _U64, _P, _U32, _P, _P]),
@@ -482,6 +483,13 @@ class ClientMatrix:
 
     def __exit__(self, *exc):
         self.close()
+
+    def set_variant(self, batch: int, variant) -> None:
+        """Kernel variant of the product for ``batch``'s bucket (index or name)."""
+        if isinstance(variant, str):
+            variant = variant_names(batch).index(variant)
+        check(lib().pir_client_mat_set_variant(self._h, batch, variant),
+              "pir_client_mat_set_variant")
 
     def workspace(self, B: int) -> torch.Tensor:
         nb = int(lib().pir_client_mat_workspace_bytes(self._h, B))

@@ -75,11 +75,6 @@ constexpr uint32_t kExactSpan = 1u << 17;     // columns one exact int32 accumul
 constexpr uint32_t kMaxExactCols = 1u << 23;  // D q < 2^64 and exact row sums
 constexpr uint32_t kMaxSplits = 16;           // split-K pieces chosen for occupancy
 
-// Byte offset of QL element (n, 0) and the offset added for column k.
-__device__ inline uint64_t ql_row(uint32_t n, uint32_t Cp) {
-    return (uint64_t)(n / 32u) * 32u * Cp + (uint64_t)(n % 32u) * 128u;
-}
-__device__ inline uint32_t ql_col(uint32_t k) { return (k >> 7) * 4096u + (k & 127u); }
 
 // Epilogue modes.
 enum : int {

@@ -172,16 +172,49 @@ __global__ void k_byte_planes(const uint32_t* __restrict__ M, uint64_t words, ui
     for (int i = 0; i < 4; ++i) row[(uint64_t)i * n + k] = (uint8_t)(w >> (8 * i));
 }
 
-// Xs[b][i n + k] = X[b][k] << 8i (mod 2^32): the secrets against the planes.
-__global__ void k_scale_secrets(const uint32_t* __restrict__ X, uint32_t B, uint32_t n,
-                                uint32_t* __restrict__ Xs) {
-    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (uint64_t)B * n) return;
-    const uint64_t b = idx / n, k = idx % n;
-    const uint32_t x = X[idx];
-    uint32_t* dst = Xs + b * 4u * n + k;
+// The batched Answer's operand for the secrets against the planes,
+// xs_b = [x_b; 2^8 x_b; 2^16 x_b; 2^24 x_b] (mod 2^32, 4n words), written
+// straight in its wide limb layout: block b writes the four limb rows of
+// query b over all Cp columns (zero past 4n, all zero for the padding
+// queries b >= B) and the exact sum of xs_b, so no clearing pass and no
+// atomics are needed.
+__global__ __launch_bounds__(256) void k_client_planes(const uint32_t* __restrict__ X,
+                                                       uint32_t B, uint32_t n, uint32_t Cp,
+                                                       int8_t* __restrict__ QL,
+                                                       uint64_t* __restrict__ colsum) {
+    __shared__ uint64_t s_sum[256];
+    const uint32_t b = blockIdx.x;
+    const bool live = b < B;
+    const uint32_t K = 4u * n;
+    const uint32_t nrow = (b / 32u) * 128u + b % 32u;   // limb 0 row; limb L adds 32 L
+    uint64_t sum = 0;
+    for (uint32_t k = 4u * threadIdx.x; k < Cp; k += 4u * blockDim.x) {
+        uint32_t word[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) dst[(uint64_t)i * n] = x << (8 * i);
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t j = k + (uint32_t)c;
+            uint32_t w = 0;
+            if (live && j < K) {
+                w = X[(uint64_t)b * n + j % n] << (8u * (j / n));
+                sum += w;
+            }
+#pragma unroll
+            for (int L = 0; L < 4; ++L) {
+                const uint32_t byte = (live && j < K) ? (((w >> (8 * L)) & 0xFFu) ^ 0x80u) : 0u;
+                word[L] |= byte << (8 * c);
+            }
+        }
+#pragma unroll
+        for (int L = 0; L < 4; ++L)
+            *reinterpret_cast<uint32_t*>(QL + ql_row(nrow + 32u * L, Cp) + ql_col(k)) = word[L];
+    }
+    s_sum[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) colsum[b] = live ? s_sum[0] : 0u;
 }
 
 // Query epilogue, in place on the product: Qt[b][j] += E[b][j] (+ Delta at
@@ -222,28 +255,32 @@ namespace {
 
 bool mat_ok(const pir_client_mat_t* m) { return m && m->magic == kClientMatMagic; }
 
-// Workspace layout of a batch of B: scaled secrets, the product (decode
-// only), then the batched Answer's own workspace.
+// Workspace layout of a batch of B: the secrets' limb planes and column
+// sums, the product (decode only), then the batched Answer's workspace.
 struct MatWs {
-    size_t xs_off, y_off, ans_off, total;
+    size_t planes_off, y_off, ans_off, total;
 };
 
 MatWs mat_ws(const pir_client_mat_t* m, uint32_t B, bool decode) {
     MatWs w;
-    w.xs_off = 0;
-    w.y_off = round_up((size_t)B * 4u * m->n * 4u, kWsAlign);
+    w.planes_off = 0;
+    w.y_off = round_up(mfma_planes_bytes(m->db, B), kWsAlign);
     w.ans_off = w.y_off + (decode ? round_up((size_t)B * m->rows * 4u, kWsAlign) : 0);
     w.total = w.ans_off + pir_workspace_bytes(m->db, B);
     return w;
 }
 
-// Y[b] = M X[b] for the B secrets into y (B x rows words).
+// Y[b] = M X[b] for the B secrets into y (B x rows words); `plan` made with
+// pre-ingested planes.
 pir_status mat_product(pir_client_mat_t* m, const uint32_t* X, uint32_t B, uint32_t* y,
-                       uint8_t* ws, const MatWs& w, hipStream_t st) {
-    uint32_t* xs = reinterpret_cast<uint32_t*>(ws + w.xs_off);
-    k_scale_secrets<<<grid1d((uint64_t)B * m->n), 256, 0, st>>>(X, B, m->n, xs);
+                       uint8_t* ws, const MatWs& w, const BatchPlan& plan, hipStream_t st) {
+    uint8_t* planes = ws + w.planes_off;
+    k_client_planes<<<plan.Bp, 256, 0, st>>>(X, B, m->n, plan.Cp,
+                                             reinterpret_cast<int8_t*>(planes),
+                                             reinterpret_cast<uint64_t*>(planes + plan.colsum_off));
     PIR_LAUNCH_CHECK();
-    return pir_answer_batch_qmajor(m->db, xs, B, y, ws + w.ans_off, w.total - w.ans_off, st);
+    const BatchIO io{nullptr, 1, 4u * m->n, y, 1, m->rows};   // query-major answers
+    return mfma_run_batch(m->db, io, B, nullptr, 0, plan, ws + w.ans_off, planes, st);
 }
 
 }  // namespace
@@ -281,6 +318,15 @@ pir_status pir_client_mat_open(const uint32_t* d_M, uint32_t rows, uint32_t n,
         delete m;
         return s;
     }
+    // The product's default tile: a 128 x 128 ring with two 128-byte stages,
+    // two workgroups per CU (the client product has K = 4n, small beside
+    // its rows).  Measured at 32768 x 1024 words, whole query call: 16
+    // secrets 39 us against 44 us with the database default, 64 secrets 54
+    // against 60 us.  pir_client_mat_set_variant overrides it.
+    for (uint32_t v = 1; v < mfma_variant_count(); ++v) {
+        if (strcmp(mfma_variant_name(v), "ring_128x128_k128_s2") != 0) continue;
+        for (uint32_t b = 8; b <= kMaxBatch; b *= 2) (void)pir_db_set_variant(m->db, b, v);
+    }
     m->magic = kClientMatMagic;
     *out = m;
     return PIR_OK;
@@ -294,6 +340,11 @@ pir_status pir_client_mat_close(pir_client_mat_t* m) {
     m->magic = 0;
     delete m;
     return st;
+}
+
+pir_status pir_client_mat_set_variant(pir_client_mat_t* m, uint32_t batch, uint32_t variant) {
+    if (!mat_ok(m) || batch == 0 || (batch & PIR_VARIANT_ROWS)) return PIR_ERR_INVALID_ARG;
+    return pir_db_set_variant(m->db, batch, variant);
 }
 
 size_t pir_client_mat_workspace_bytes(const pir_client_mat_t* m, uint32_t B) {
@@ -315,9 +366,9 @@ pir_status pir_client_query_mat(pir_client_mat_t* A, const uint32_t* d_S, const 
     const MatWs w = mat_ws(A, B, false);
     const hipStream_t st = static_cast<hipStream_t>(stream);
     BatchPlan plan;   // every check of the product before anything is enqueued
-    pir_status s = mfma_plan_batch(A->db, B, nullptr, 0, 0, false, &plan);
+    pir_status s = mfma_plan_batch(A->db, B, nullptr, 0, 0, true, &plan);
     if (s != PIR_OK) return s;
-    s = mat_product(A, d_S, B, d_Qt, static_cast<uint8_t*>(d_ws), w, st);
+    s = mat_product(A, d_S, B, d_Qt, static_cast<uint8_t*>(d_ws), w, plan, st);
     if (s != PIR_OK) return s;
     k_query_epilogue<<<grid1d((uint64_t)B * A->rows), 256, 0, st>>>(d_Qt, A->rows, B, d_E, d_cols);
     PIR_LAUNCH_CHECK();
@@ -338,11 +389,11 @@ pir_status pir_client_decode_mat(pir_client_mat_t* H, const uint32_t* d_S,
     const MatWs w = mat_ws(H, B, true);
     const hipStream_t st = static_cast<hipStream_t>(stream);
     BatchPlan plan;
-    pir_status s = mfma_plan_batch(H->db, B, nullptr, 0, 0, false, &plan);
+    pir_status s = mfma_plan_batch(H->db, B, nullptr, 0, 0, true, &plan);
     if (s != PIR_OK) return s;
     uint8_t* ws = static_cast<uint8_t*>(d_ws);
     uint32_t* y = reinterpret_cast<uint32_t*>(ws + w.y_off);
-    s = mat_product(H, d_S, B, y, ws, w, st);
+    s = mat_product(H, d_S, B, y, ws, w, plan, st);
     if (s != PIR_OK) return s;
     const uint64_t count = (uint64_t)B * H->rows;
     k_decode_epilogue<<<grid1d(count), 256, 0, st>>>(y, d_answers, count, d_out);

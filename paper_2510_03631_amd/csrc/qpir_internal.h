@@ -61,6 +61,17 @@ struct BatchIO {
     uint64_t o_ldr, o_ldb;
 };
 
+// Limb planes of a batch (the matrix-core path's B operand): row n holds
+// one limb of one query, entries byte ^ 0x80 as int8, zero-padded to Cp
+// columns, stored in 4 KiB tiles of 32 rows x 128 bytes, tile (n/32, k/128)
+// at ((n/32) Cp/128 + k/128) 4096.  Byte offset of element (n, 0), and the
+// offset added for column k.  Wide layout: row (b/32) 128 + 32 limb + b%32
+// for query b.
+__device__ inline uint64_t ql_row(uint32_t n, uint32_t Cp) {
+    return (uint64_t)(n / 32u) * 32u * Cp + (uint64_t)(n % 32u) * 128u;
+}
+__device__ inline uint32_t ql_col(uint32_t k) { return (k >> 7) * 4096u + (k & 127u); }
+
 // ---- single-query path (answer_gemv.hip)
 uint32_t gemv_variant_count();
 const char* gemv_variant_name(uint32_t v);

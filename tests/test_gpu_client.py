@@ -182,3 +182,29 @@ def test_client_matrix_core_errors(qp):
                                         Qt.data_ptr(), ws.data_ptr(), ws.numel(), None) == 2
         torch.cuda.synchronize()
         assert int((Qt != 5).sum().item()) == 0   # nothing written
+
+
+def test_client_matrix_core_every_variant(qp):
+    """Every product variant a prepared client matrix can take gives the
+    oracle's queries (the secrets' operand is written straight into the
+    wide limb layout, which every wide variant reads)."""
+    from paper_2510_03631_amd._lib import variant_names
+    banner("client matrix cores: every variant")
+    g = workload.rng(4711)
+    C, n, B = 700, 128, 40
+    A = workload.uniform_u32(g, (C, n))
+    dr = workload.lwe_draws(g, C, n, B)
+    exp = np.stack([oracle.lwe_query(A, dr.s[b], dr.e[b], int(dr.col[b])) for b in range(B)])
+    tried = 0
+    with qp.ClientMatrix(to_dev_u32(A)) as Am:
+        Sd, Ed = to_dev_u32(dr.s), _dev_i32(dr.e)
+        cd = to_dev_u32(dr.col.astype(np.uint32))
+        for v, name in enumerate(variant_names(B)):
+            try:
+                Am.set_variant(B, v)
+            except qp.PirError:
+                continue
+            banner(f"client matrix cores variant {name}")
+            assert np.array_equal(to_host_u32(Am.query(Sd, Ed, cd)), exp), name
+            tried += 1
+    assert tried >= 4
