@@ -556,9 +556,15 @@ __device__ inline void ring_barrier() {
 // staging), into a ring of STAGES k-tiles of BK bytes, so STAGES-1 tiles are
 // in flight while one is consumed.  Centring of D (xor 0x80) is applied to
 // the A fragments in registers.
-template <int WM_, int WN_, int TM_, int TN_, int STAGES_, int BK_ = 64, bool NARROW_ = false>
+// DX_ > 0 gives D DX_ more ring slots than the limb planes (SA = STAGES +
+// DX_ D tiles against SB = STAGES QL tiles): D tiles are then issued DX_
+// stages earlier than the QL tiles they meet.
+template <int WM_, int WN_, int TM_, int TN_, int STAGES_, int BK_ = 64, bool NARROW_ = false,
+          int DX_ = 0>
 struct Ring {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, STAGES = STAGES_;
+    static constexpr int DX = DX_;
+    static constexpr int SA = STAGES + DX, SB = STAGES;   // D and QL ring slots
     static constexpr bool NARROW = NARROW_;              // narrow QL layout (8 queries per tile)
     static constexpr int NW = WM * WN;                   // waves per workgroup
     static constexpr int THREADS = 64 * NW;
@@ -568,17 +574,28 @@ struct Ring {
     static constexpr int BM = WM * TM * 32;
     static constexpr int BN = WN * TN * 32;
     static constexpr int A_BYTES = BM * BK;
+    static constexpr int B_BYTES = BN * BK;
     static constexpr int STAGE_BYTES = (BM + BN) * BK;
     static constexpr int A_BLOCKS = BM / RPB;            // 1 KiB blocks
     static constexpr int BLOCKS = (BM + BN) / RPB;
     static constexpr int LOADS = BLOCKS / NW;            // per wave per tile
-    static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
+    static constexpr int LDS_BYTES = SA * A_BYTES + SB * B_BYTES;
     static_assert(BK == 64 || BK == 128, "64- or 128-byte stages");
     static_assert(NW == 4 || NW == 8, "four or eight waves");
     static_assert(NARROW || TN % 4 == 0, "a wave covers whole groups of four limbs");
     static_assert(BLOCKS % NW == 0, "blocks split evenly over waves");
     static_assert(A_BLOCKS % NW == 0, "a wave's first A_LOADS loads carry D rows");
     static constexpr int A_LOADS = A_BLOCKS / NW;
+    static constexpr int B_LOADS = LOADS - A_LOADS;
+    // Per stage a wave issues LOADS loads, one list: D first then QL (DX
+    // == 0), or QL first then D (DX > 0, so the D tile issued after a QL tile
+    // may stay in flight while that QL tile is consumed).  Loads complete in
+    // order; at the start of stage u at most QL_WAIT of this wave's loads
+    // may still be outstanding for tiles u (D and QL) to have landed: with
+    // DX == 0 the stages after the one that issued D(u) (its last load);
+    // with DX > 0 that stage's D loads plus the stages after the one that
+    // issued QL(u).
+    static constexpr int QL_WAIT = (DX > 0 ? A_LOADS : 0) + (STAGES - 2) * LOADS;
     // The loads of the tile that refills a freed slot are spread over all
     // KS k-steps of a stage when another tile is in flight (three or more
     // stages), else over the fewest k-steps that fit (one load per MFMA),
@@ -586,7 +603,8 @@ struct Ring {
     static constexpr int KS = BK / 32;
     static constexpr int FIT = (LOADS + TM * TN - 1) / (TM * TN);
     static constexpr int ISSUE_STEPS = STAGES > 2 ? KS : (FIT < KS ? FIT : KS);
-    static_assert((STAGES - 2) * LOADS < 64, "vmcnt range");
+    static_assert(QL_WAIT < 64, "vmcnt range");
+    static_assert(STAGES >= 2, "one tile in flight while one is consumed");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
@@ -620,11 +638,18 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     const int lrow = lane / T::SEGS;
     const uint8_t* src[T::LOADS];
     uint32_t seg_off[T::LOADS];
+    // Load i of a stage's list: a D load (is_a) and its block index within
+    // the D or QL part of the tile.
+    auto is_a = [](int i) { return T::DX > 0 ? i >= T::B_LOADS : i < T::A_LOADS; };
+    auto blk = [](int i) {
+        return T::DX > 0 ? (i >= T::B_LOADS ? i - T::B_LOADS : i)
+                         : (i < T::A_LOADS ? i : i - T::A_LOADS);
+    };
 #pragma unroll
     for (int i = 0; i < T::LOADS; ++i) {
-        const bool a = i < T::A_LOADS;
-        const int kb = wave + T::NW * i;
-        const int r = (a ? kb : kb - T::A_BLOCKS) * T::RPB + lrow;
+        const bool a = is_a(i);
+        const int kb = wave + T::NW * blk(i);
+        const int r = kb * T::RPB + lrow;
         const int seg = swz<T::BK>(r, lane % T::SEGS);
         seg_off[i] = 16u * seg;
         if (a) {
@@ -645,16 +670,25 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     // * t past the piece's last tile is clamped to it: such a load refills a
     //   slot no later iteration reads.
     const uint32_t t_last = ktiles ? ktiles - 1 : 0;
-    auto issue_one = [&](uint32_t t, int i) {
+    uint8_t* const ringA = smem;                          // SA D tiles
+    uint8_t* const ringB = smem + T::SA * T::A_BYTES;     // SB QL tiles
+    // Load i of the list issued at stage u: D tile u + SA - 1 or QL tile
+    // u + SB - 1 (DX == 0: the same tile u + STAGES - 1).
+    auto issue_tile = [&](uint32_t t, int i) {
+        const bool a = is_a(i);
         const uint32_t tt = min(t, t_last);
         const uint32_t k0 = (kt0 + tt) * T::BK;
-        uint8_t* dst = smem + (t % T::STAGES) * T::STAGE_BYTES + (wave + T::NW * i) * 1024;
-        const uint8_t* p = i < T::A_LOADS ? src[i] + min(k0 + seg_off[i], C - 16u)
-                                          : src[i] + ql_col(k0);   // BK divides 128
-        if (NTD && i < T::A_LOADS)   // D read once: non-temporal
+        uint8_t* dst = (a ? ringA + (t % T::SA) * T::A_BYTES : ringB + (t % T::SB) * T::B_BYTES) +
+                       (wave + T::NW * blk(i)) * 1024;
+        const uint8_t* p = a ? src[i] + min(k0 + seg_off[i], C - 16u)
+                             : src[i] + ql_col(k0);   // BK divides 128
+        if (NTD && a)   // D read once: non-temporal
             __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)dst, 16, 0, kCpolNT);
         else
             __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)dst, 16, 0, 0);
+    };
+    auto issue_one = [&](uint32_t u, int i) {
+        issue_tile(u + (is_a(i) ? T::SA : T::SB) - 1, i);
     };
 
     i32x16 acc[T::TM][T::TN];
@@ -674,8 +708,8 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     u32x4 fa[2][T::TM];
     i32x4 fb[2][T::TN];
     auto read_frags = [&](uint32_t u, int ks, int buf) {
-        const uint8_t* sa = smem + (u % T::STAGES) * T::STAGE_BYTES;
-        const uint8_t* sb = sa + T::A_BYTES;
+        const uint8_t* sa = ringA + (u % T::SA) * T::A_BYTES;
+        const uint8_t* sb = ringB + (u % T::SB) * T::B_BYTES;
         const int seg = 2 * ks + fseg;
 #pragma unroll
         for (int a = 0; a < T::TM; ++a) {
@@ -689,10 +723,10 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
         }
     };
     // One k-step of MFMAs (centred A fragments ac, B buffer buf) with loads
-    // lo .. hi-1 of tile t placed between them, one after each MFMA (VMEM
-    // and MFMA scheduling groups); narrow tiles, with more loads than MFMAs,
-    // issue the rest after the last MFMA.
-    auto mfma_step = [&](const i32x4 (&ac)[T::TM], int buf, uint32_t t, int lo, int hi) {
+    // lo .. hi-1 of stage u's list placed between them, one after each MFMA
+    // (VMEM and MFMA scheduling groups); narrow tiles, with more loads than
+    // MFMAs, issue the rest after the last MFMA.
+    auto mfma_step = [&](const i32x4 (&ac)[T::TM], int buf, uint32_t u, int lo, int hi) {
         constexpr int kMfma = T::TM * T::TN;
 #pragma unroll
         for (int a = 0; a < T::TM; ++a)
@@ -700,7 +734,7 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
             for (int b = 0; b < T::TN; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[a], fb[buf][b], acc[a][b], 0, 0, 0);
 #pragma unroll
-        for (int i = lo; i < hi; ++i) issue_one(t, i);
+        for (int i = lo; i < hi; ++i) issue_one(u, i);
         const int paired = hi - lo < kMfma ? hi - lo : kMfma;
 #pragma unroll
         for (int j = 0; j < paired; ++j) {
@@ -718,22 +752,27 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
         return j < T::ISSUE_STEPS ? j * T::LOADS / T::ISSUE_STEPS : T::LOADS;
     };
 
+    // The lists of the stages before the first, in the same order: stage v
+    // (v = -(SA-1) .. -1) issues the tiles of its list that exist.
     if (ktiles > 0) {
 #pragma unroll
-        for (int p = 0; p < T::STAGES - 1; ++p)
+        for (int v = -(T::SA - 1); v < 0; ++v)
 #pragma unroll
-            for (int i = 0; i < T::LOADS; ++i) issue_one(p, i);
+            for (int i = 0; i < T::LOADS; ++i) {
+                const int t = v + (is_a(i) ? T::SA : T::SB) - 1;
+                if (t >= 0) issue_tile((uint32_t)t, i);
+            }
     }
 
     for (uint32_t u = 0; u < ktiles; ++u) {
-        // Tiles u+1 .. u+STAGES-2 (LOADS loads each) were issued after tile
-        // u and loads complete in order, so tile u has landed once at most
+        // The loads issued after tile u's (see QL_WAIT) may still be in
+        // flight; loads complete in order, so tile u has landed once at most
         // that many of this wave's loads are outstanding.  The barrier then
-        // makes every wave's part visible and frees the slot of tile u-1
+        // makes every wave's part visible and frees the slots of tile u-1
         // (every wave's reads of it have returned: the last MFMAs of tile
-        // u-1 waited for them), which is refilled with tile u+STAGES-1
-        // while tile u is consumed.
-        wait_vmcnt<(T::STAGES - 2) * T::LOADS>();
+        // u-1 waited for them), which are refilled with D tile u+SA-1 and
+        // QL tile u+SB-1 while tile u is consumed.
+        wait_vmcnt<T::QL_WAIT>();
         ring_barrier();
 
         // Per k-step: centre the A fragments, read the fragments of the next
@@ -742,7 +781,6 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
         // back to back waits on the address unit with no MFMA to run
         // (measured: about 40% of the loop); between MFMAs the waits overlap
         // them.  The scheduling barriers keep this order.
-        const uint32_t t_next = u + T::STAGES - 1;
         read_frags(u, 0, 0);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -752,7 +790,7 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
             __builtin_amdgcn_sched_barrier(0);
             if (ks + 1 < KS) read_frags(u, ks + 1, (ks + 1) & 1);
             __builtin_amdgcn_sched_barrier(0);
-            mfma_step(a_c, ks & 1, t_next, first_load(ks), first_load(ks + 1));
+            mfma_step(a_c, ks & 1, u, first_load(ks), first_load(ks + 1));
         }
     }
     // Loads past the last tile may still be landing in LDS.
@@ -1050,6 +1088,10 @@ using Ring128x256S6 = Ring<2, 2, 2, 4, 6>;              // 144 KiB
 using Ring8w128x256K128S3 = Ring<4, 2, 1, 4, 3, 128>;   // 8 waves, 144 KiB
 using Ring8w256x256S4 = Ring<4, 2, 2, 4, 4>;            // 8 waves, 128 KiB
 using Ring8w256x256K128S2 = Ring<4, 2, 2, 4, 2, 128>;   // 8 waves, 128 KiB
+// The same with a third D slot (D two tiles ahead, QL one): 160 KiB.
+using Ring8w256x256K128D3 = Ring<4, 2, 2, 4, 2, 128, false, 1>;
+// 128 x 256 with four D slots and three QL slots: 160 KiB.
+using Ring8w128x256K128D4 = Ring<4, 2, 1, 4, 3, 128, false, 1>;
 using Ring256x256K128S2 = Ring<2, 2, 4, 4, 2, 128>;     // 4 waves of 128 x 128, 128 KiB
 // Two workgroups per CU (64 KiB each): the waves sharing a SIMD belong to
 // different workgroups, so one's barrier does not idle the other.
@@ -1092,6 +1134,8 @@ const VariantInfo kVariants[] = {
     {"narrow_256x32_k128_s4", kRing, 256, 32, 128, launch_ring<Narrow256x32K128S4>, 1, true},
     {"narrow_256x64_k128_s4", kRing, 256, 64, 128, launch_ring<Narrow256x64K128S4>, 1, true},
     {"narrow_128x32_k128_s6", kRing, 128, 32, 128, launch_ring<Narrow128x32K128S6>, 1, true},
+    {"ring8w_256x256_k128_d3q2", kRing, 256, 256, 128, launch_ring<Ring8w256x256K128D3>},
+    {"ring8w_128x256_k128_d4q3", kRing, 128, 256, 128, launch_ring<Ring8w128x256K128D4>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
@@ -1272,6 +1316,8 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Narrow256x32K128S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Narrow256x64K128S4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Narrow128x32K128S6>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w256x256K128D3>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w128x256K128D4>()) != PIR_OK) return st;
     if ((st = set_roles_lds<Roles256x256A5B4>()) != PIR_OK) return st;
     return set_roles_lds<Roles128x256A10B4>();
 }
