@@ -557,14 +557,17 @@ __device__ inline void ring_barrier() {
 // in flight while one is consumed.  Centring of D (xor 0x80) is applied to
 // the A fragments in registers.
 // DX_ > 0 gives D DX_ more ring slots than the limb planes (SA = STAGES +
-// DX_ D tiles against SB = STAGES QL tiles): D tiles are then issued DX_
-// stages earlier than the QL tiles they meet.
+// DX_ D tiles against SB = STAGES QL tiles), QX_ > 0 the limb planes QX_
+// more than D: the deeper operand's tiles are issued that many stages
+// earlier than the tiles of the other they meet.
 template <int WM_, int WN_, int TM_, int TN_, int STAGES_, int BK_ = 64, bool NARROW_ = false,
-          int DX_ = 0>
+          int DX_ = 0, int QX_ = 0>
 struct Ring {
     static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, STAGES = STAGES_;
-    static constexpr int DX = DX_;
-    static constexpr int SA = STAGES + DX, SB = STAGES;   // D and QL ring slots
+    static constexpr int DX = DX_, QX = QX_;
+    static constexpr int SA = STAGES + DX, SB = STAGES + QX;   // D and QL ring slots
+    static constexpr int SMAX = SA > SB ? SA : SB;
+    static_assert(DX == 0 || QX == 0, "one operand runs deeper");
     static constexpr bool NARROW = NARROW_;              // narrow QL layout (8 queries per tile)
     static constexpr int NW = WM * WN;                   // waves per workgroup
     static constexpr int THREADS = 64 * NW;
@@ -588,14 +591,14 @@ struct Ring {
     static constexpr int A_LOADS = A_BLOCKS / NW;
     static constexpr int B_LOADS = LOADS - A_LOADS;
     // Per stage a wave issues LOADS loads, one list: D first then QL (DX
-    // == 0), or QL first then D (DX > 0, so the D tile issued after a QL tile
-    // may stay in flight while that QL tile is consumed).  Loads complete in
-    // order; at the start of stage u at most QL_WAIT of this wave's loads
-    // may still be outstanding for tiles u (D and QL) to have landed: with
-    // DX == 0 the stages after the one that issued D(u) (its last load);
-    // with DX > 0 that stage's D loads plus the stages after the one that
-    // issued QL(u).
-    static constexpr int QL_WAIT = (DX > 0 ? A_LOADS : 0) + (STAGES - 2) * LOADS;
+    // == 0), or QL first then D (DX > 0): the deeper operand goes last, so
+    // its tile issued after the other's may stay in flight while that one
+    // is consumed.  Loads complete in order; at the start of stage u at most
+    // QL_WAIT of this wave's loads may still be outstanding for tiles u (D
+    // and QL) to have landed: the deeper operand's loads of the stage that
+    // issued the other operand's tile u, plus the stages after it.
+    static constexpr int QL_WAIT =
+        (DX > 0 ? A_LOADS : 0) + (QX > 0 ? LOADS - A_LOADS : 0) + (STAGES - 2) * LOADS;
     // The loads of the tile that refills a freed slot are spread over all
     // KS k-steps of a stage when another tile is in flight (three or more
     // stages), else over the fewest k-steps that fit (one load per MFMA),
@@ -753,10 +756,10 @@ __global__ __launch_bounds__(T::THREADS) void k_gemm_ring(const uint8_t* __restr
     };
 
     // The lists of the stages before the first, in the same order: stage v
-    // (v = -(SA-1) .. -1) issues the tiles of its list that exist.
+    // (v = -(max(SA, SB)-1) .. -1) issues the tiles of its list that exist.
     if (ktiles > 0) {
 #pragma unroll
-        for (int v = -(T::SA - 1); v < 0; ++v)
+        for (int v = -(T::SMAX - 1); v < 0; ++v)
 #pragma unroll
             for (int i = 0; i < T::LOADS; ++i) {
                 const int t = v + (is_a(i) ? T::SA : T::SB) - 1;
@@ -1092,6 +1095,14 @@ using Ring8w256x256K128S2 = Ring<4, 2, 2, 4, 2, 128>;   // 8 waves, 128 KiB
 using Ring8w256x256K128D3 = Ring<4, 2, 2, 4, 2, 128, false, 1>;
 // 128 x 256 with four D slots and three QL slots: 160 KiB.
 using Ring8w128x256K128D4 = Ring<4, 2, 1, 4, 3, 128, false, 1>;
+// 128 x 256 with five D slots (D four tiles ahead) and two QL slots: 144 KiB.
+using Ring8w128x256K128D5 = Ring<4, 2, 1, 4, 2, 128, false, 3>;
+// 256 x 256 with a third QL slot (limb planes two tiles ahead): 160 KiB.
+using Ring8w256x256K128Q3 = Ring<4, 2, 2, 4, 2, 128, false, 0, 1>;
+// Narrow tiles with deeper D rings: 256 x 32 with 4 D / 3 QL slots (140 KiB),
+// 128 x 32 with 8 D / 6 QL slots (152 KiB).
+using Narrow256x32K128D4 = Ring<4, 1, 2, 1, 3, 128, true, 1>;
+using Narrow128x32K128D8 = Ring<4, 1, 1, 1, 6, 128, true, 2>;
 using Ring256x256K128S2 = Ring<2, 2, 4, 4, 2, 128>;     // 4 waves of 128 x 128, 128 KiB
 // Two workgroups per CU (64 KiB each): the waves sharing a SIMD belong to
 // different workgroups, so one's barrier does not idle the other.
@@ -1136,6 +1147,10 @@ const VariantInfo kVariants[] = {
     {"narrow_128x32_k128_s6", kRing, 128, 32, 128, launch_ring<Narrow128x32K128S6>, 1, true},
     {"ring8w_256x256_k128_d3q2", kRing, 256, 256, 128, launch_ring<Ring8w256x256K128D3>},
     {"ring8w_128x256_k128_d4q3", kRing, 128, 256, 128, launch_ring<Ring8w128x256K128D4>},
+    {"ring8w_128x256_k128_d5q2", kRing, 128, 256, 128, launch_ring<Ring8w128x256K128D5>},
+    {"ring8w_256x256_k128_d2q3", kRing, 256, 256, 128, launch_ring<Ring8w256x256K128Q3>},
+    {"narrow_256x32_k128_d4q3", kRing, 256, 32, 128, launch_ring<Narrow256x32K128D4>, 1, true},
+    {"narrow_128x32_k128_d8q6", kRing, 128, 32, 128, launch_ring<Narrow128x32K128D8>, 1, true},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
@@ -1318,6 +1333,10 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Narrow128x32K128S6>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring8w256x256K128D3>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Ring8w128x256K128D4>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w128x256K128D5>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring8w256x256K128Q3>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Narrow256x32K128D4>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Narrow128x32K128D8>()) != PIR_OK) return st;
     if ((st = set_roles_lds<Roles256x256A5B4>()) != PIR_OK) return st;
     return set_roles_lds<Roles128x256A10B4>();
 }

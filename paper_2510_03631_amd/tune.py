@@ -61,7 +61,10 @@ def tune_database(db: Database, batches, reps: int = 5, log=print, modulus: int 
             A = torch.randint(-2**31, 2**31 - 1, (db.cols, B), dtype=torch.int32, device=db.device)
             H = torch.zeros((db.rows, B), dtype=torch.int32, device=db.device)
             ws = db.workspace(B)
-            fn = lambda: db.hint_update_rows(rows, A, H, ws=ws)
+            # The refresh as the library runs it: A's limb planes prepared
+            # once, each call timing the gathered product alone.
+            planes = db.hint_planes(A)
+            fn = lambda: db.hint_update_rows_planes(rows, planes, B, H, ws=ws)
         elif B == 0:
             q = torch.randint(-2**31, 2**31 - 1, (db.cols,), dtype=torch.int32, device=db.device)
             out = torch.empty(db.rows, dtype=torch.int32, device=db.device)
