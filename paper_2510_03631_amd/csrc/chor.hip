@@ -320,18 +320,31 @@ __device__ inline uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return r;
 }
 
-template <int G, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_chor_shared8(const uint32_t* __restrict__ DB,
-                                                           uint64_t pitch, uint32_t rows,
-                                                           uint32_t W,
-                                                           const uint32_t* __restrict__ Q,
-                                                           uint32_t qwords, uint32_t B,
-                                                           uint32_t slab_rows, uint32_t n_qg,
-                                                           uint32_t n_cs,
-                                                           uint32_t* __restrict__ out) {
+// NW waves of G queries share each step's two tables.  With four waves a
+// wave builds four entries of both tables; with eight, four entries of one
+// (waves 0-3 the table of rows 0-3, waves 4-7 that of rows 4-7), so the
+// build, which every step waits for at its barrier, is spread over twice the
+// queries.  Entry e of a table is hi(e >> 2) ^ lo(e & 3), hi and lo the XOR
+// combinations of the half's rows 2-3 and 0-1; wave w builds entries
+// 4c .. 4c+3 with c = w % 4.  Rows are plain loads: the query groups of a
+// slab read them from L2 (non-temporal loads fetched the database 3.8 times
+// from HBM per launch at 1024 queries, plain ones 1.5 times).
+template <int G, int NW, bool VEC>
+__global__ __launch_bounds__(64 * NW) void k_chor_shared8(const uint32_t* __restrict__ DB,
+                                                          uint64_t pitch, uint32_t rows,
+                                                          uint32_t W,
+                                                          const uint32_t* __restrict__ Q,
+                                                          uint32_t qwords, uint32_t B,
+                                                          uint32_t slab_rows, uint32_t n_qg,
+                                                          uint32_t n_cs,
+                                                          uint32_t* __restrict__ out) {
+    static_assert(NW == 4 || NW == 8, "four or eight waves");
+    constexpr int NH = NW == 4 ? 2 : 1;           // table halves a wave builds
     __shared__ u32x4 s_tab[2][2][16][64];         // [buffer][table][entry][lane], 64 KiB
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = wave & 3;                       // hi combination of the wave's entries
+    const int h0 = NW == 4 ? 0 : wave >> 2;       // first table half it builds
     const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t qg = bid % n_qg;
     const uint32_t cs = (bid / n_qg) % n_cs;
@@ -340,105 +353,102 @@ __global__ __launch_bounds__(kThreads) void k_chor_shared8(const uint32_t* __res
     const uint32_t r1 = min(rows, r0 + slab_rows);
     const uint32_t w = cs * 256u + 4u * lane;
     const bool active = w < W;
-    const uint32_t qbase = (qg * 4u + (uint32_t)wave) * G;
+    const uint32_t qbase = (qg * (uint32_t)NW + (uint32_t)wave) * G;
     const uint32_t nq = qbase < B ? min((uint32_t)G, B - qbase) : 0u;
 
-    if (wave < 2) {
-        s_tab[wave][0][0][lane] = u32x4{0, 0, 0, 0};
-        s_tab[wave][1][0][lane] = u32x4{0, 0, 0, 0};
+    if (c == 0) {                                 // entry 0 of the wave's halves
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < NH; ++i) s_tab[b][h0 + i][0][lane] = u32x4{0, 0, 0, 0};
     }
     u32x4 acc[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) acc[g] = u32x4{0, 0, 0, 0};
 
-    // Rows of each 4-row half this wave needs for its entries: 0 and 1
-    // always; 2 for waves 1 and 3; 3 for waves 2 and 3.
-    const bool need2 = wave == 1 || wave == 3;
-    const bool need3 = wave >= 2;
+    // Rows of each 4-row half the wave needs: 0 and 1 always; 2 if c & 1;
+    // 3 if c & 2.
+    const bool need2 = (c & 1) != 0;
+    const bool need3 = (c & 2) != 0;
     auto load_row = [&](uint32_t r) -> u32x4 {
-        return (active && r < r1) ? load_words_nt<VEC>(DB + (uint64_t)r * pitch, w, W)
+        return (active && r < r1) ? load_words<VEC>(DB + (uint64_t)r * pitch, w, W)
                                   : u32x4{0, 0, 0, 0};
     };
-    auto load_step = [&](uint32_t st, u32x4 (&x)[8]) {
+    auto load_step = [&](uint32_t st, u32x4 (&x)[4 * NH]) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t r = r0 + 8u * st + 4u * h;
-            x[4 * h + 0] = load_row(r);
-            x[4 * h + 1] = load_row(r + 1);
-            x[4 * h + 2] = need2 ? load_row(r + 2) : u32x4{0, 0, 0, 0};
-            x[4 * h + 3] = need3 ? load_row(r + 3) : u32x4{0, 0, 0, 0};
+        for (int i = 0; i < NH; ++i) {
+            const uint32_t r = r0 + 8u * st + 4u * (uint32_t)(h0 + i);
+            x[4 * i + 0] = load_row(r);
+            x[4 * i + 1] = load_row(r + 1);
+            x[4 * i + 2] = need2 ? load_row(r + 2) : u32x4{0, 0, 0, 0};
+            x[4 * i + 3] = need3 ? load_row(r + 3) : u32x4{0, 0, 0, 0};
         }
     };
-    // Selector words of the wave's G queries for one 32-row block (scalar
-    // loads for G <= 16, one lane per query above; see k_chor_shared).
-    constexpr bool kScalarSel = G <= 16;
-    auto load_sel = [&](uint32_t blk, uint32_t (&sel)[G]) {
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const uint32_t b = min(qbase + (uint32_t)g, B - 1u);
-            sel[g] = 32u * blk < rows ? Q[(uint64_t)b * qwords + blk] : 0u;
-        }
-    };
+    // Selector words of the wave's G queries for one 32-row block, one lane
+    // per query (scalar selector words would spill SGPRs at 32 queries).
     auto load_sel_lane = [&](uint32_t blk) -> uint32_t {
         const uint32_t b = qbase + (uint32_t)lane;
         return ((uint32_t)lane < nq && 32u * blk < rows) ? Q[(uint64_t)b * qwords + blk] : 0u;
     };
 
     const uint32_t nsteps = r1 > r0 ? (r1 - r0 + 7u) / 8u : 0u;
-    u32x4 xa[8], xb[8];
+    u32x4 xa[4 * NH], xb[4 * NH];
     load_step(0, xa);
     load_step(1, xb);
-    uint32_t qv[kScalarSel ? G : 1];
-    uint32_t qlane = 0, qlane_next = kScalarSel ? 0u : load_sel_lane(r0 / 32u);
+    uint32_t qlane = 0, qlane_next = load_sel_lane(r0 / 32u);
 
-    auto step = [&](uint32_t st, u32x4 (&x)[8]) {
+    auto step = [&](uint32_t st, u32x4 (&x)[4 * NH]) {
         const int buf = st & 1;
         if (st % 4u == 0) {
-            if constexpr (kScalarSel) {
-                load_sel(r0 / 32u + st / 4u, qv);
-            } else {
-                qlane = qlane_next;
-                qlane_next = load_sel_lane(r0 / 32u + st / 4u + 1u);
-            }
+            qlane = qlane_next;
+            qlane_next = load_sel_lane(r0 / 32u + st / 4u + 1u);
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const u32x4 lo1 = x[4 * h], lo2 = x[4 * h + 1], lo3 = lo1 ^ lo2;
-            const u32x4 hi = wave == 0 ? u32x4{0, 0, 0, 0}
-                                       : (wave == 1 ? x[4 * h + 2]
-                                                    : (wave == 2 ? x[4 * h + 3]
-                                                                 : x[4 * h + 2] ^ x[4 * h + 3]));
-            if (wave != 0) s_tab[buf][h][4 * wave][lane] = hi;
-            s_tab[buf][h][4 * wave + 1][lane] = hi ^ lo1;
-            s_tab[buf][h][4 * wave + 2][lane] = hi ^ lo2;
-            s_tab[buf][h][4 * wave + 3][lane] = hi ^ lo3;
+        for (int i = 0; i < NH; ++i) {
+            const u32x4 lo1 = x[4 * i], lo2 = x[4 * i + 1], lo3 = lo1 ^ lo2;
+            const u32x4 hi = c == 0 ? u32x4{0, 0, 0, 0}
+                                    : (c == 1 ? x[4 * i + 2]
+                                              : (c == 2 ? x[4 * i + 3]
+                                                        : x[4 * i + 2] ^ x[4 * i + 3]));
+            if (c != 0) s_tab[buf][h0 + i][4 * c][lane] = hi;
+            s_tab[buf][h0 + i][4 * c + 1][lane] = hi ^ lo1;
+            s_tab[buf][h0 + i][4 * c + 2][lane] = hi ^ lo2;
+            s_tab[buf][h0 + i][4 * c + 3][lane] = hi ^ lo3;
         }
         if (st + 2u < nsteps) load_step(st + 2u, x);    // prefetch two steps ahead
         lds_barrier();
         const int sh = 8 * (int)(st % 4u);
-        // Lookups in groups of KG queries (4 for 32 queries per wave, which
-        // keeps the kernel within 256 registers: two waves per SIMD).
-        constexpr int KG = G >= 32 ? 4 : 8;
+        // Lookups in groups of two queries, software-pipelined: the LDS reads
+        // of group j+1 are issued before the XORs of group j, so the XORs
+        // overlap the reads' latency (measured at 1024 queries: 3.64 ->
+        // 3.35 ms against groups of four read and then XORed).  Two buffers
+        // of two queries hold as many registers as one group of four.
+        constexpr int PK = 2;
+        constexpr int NG = G / PK;
+        u32x4 t0[2][PK], t1[2][PK];
+        auto lookups = [&](int j, int bsel) {
 #pragma unroll
-        for (int g0 = 0; g0 < G; g0 += KG) {
-            u32x4 t0[KG], t1[KG];
-#pragma unroll
-            for (int g = 0; g < KG && g0 + g < G; ++g) {
-                const uint32_t word = kScalarSel ? qv[kScalarSel ? g0 + g : 0]
-                                                 : __builtin_amdgcn_readlane(qlane, g0 + g);
-                t0[g] = s_tab[buf][0][(word >> sh) & 15u][lane];
-                t1[g] = s_tab[buf][1][(word >> (sh + 4)) & 15u][lane];
+            for (int g = 0; g < PK; ++g) {
+                const uint32_t word = __builtin_amdgcn_readlane(qlane, j * PK + g);
+                t0[bsel][g] = s_tab[buf][0][(word >> sh) & 15u][lane];
+                t1[bsel][g] = s_tab[buf][1][(word >> (sh + 4)) & 15u][lane];
             }
+        };
+        lookups(0, 0);
 #pragma unroll
-            for (int g = 0; g < KG && g0 + g < G; ++g) {
-                u32x4& a = acc[g0 + g];   // a ^ t0 ^ t1 in one instruction per word
-                a.x = xor3(a.x, t0[g].x, t1[g].x);
-                a.y = xor3(a.y, t0[g].y, t1[g].y);
-                a.z = xor3(a.z, t0[g].z, t1[g].z);
-                a.w = xor3(a.w, t0[g].w, t1[g].w);
+        for (int j = 0; j < NG; ++j) {
+            if (j + 1 < NG) lookups(j + 1, (j + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = 0; g < PK; ++g) {
+                u32x4& a = acc[j * PK + g];   // a ^ t0 ^ t1 in one instruction per word
+                const u32x4& y0 = t0[j & 1][g];
+                const u32x4& y1 = t1[j & 1][g];
+                a.x = xor3(a.x, y0.x, y1.x);
+                a.y = xor3(a.y, y0.y, y1.y);
+                a.z = xor3(a.z, y0.z, y1.z);
+                a.w = xor3(a.w, y0.w, y1.w);
             }
-            // Keep the groups apart: hoisting every group's reads would hold
-            // them all in registers at once.
             __builtin_amdgcn_sched_barrier(0);
         }
     };
@@ -461,12 +471,15 @@ __global__ __launch_bounds__(kThreads) void k_chor_shared8(const uint32_t* __res
     }
 }
 
-template <int G, bool EIGHT = false>
+// NW8 = 0: the 4-row kernel (four waves); 4 or 8: the 8-row kernel with
+// that many waves per workgroup.
+template <int G, int NW8 = 0>
 pir_status launch_shared(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_t pitch,
                          const uint32_t* d_Q, uint32_t B, uint32_t* d_out, uint32_t target,
                          hipStream_t s) {
+    constexpr int NW = NW8 ? NW8 : 4;
     const uint32_t qwords = (rows + 31) / 32;
-    const uint32_t n_qg = (B + 4 * G - 1) / (4 * G);
+    const uint32_t n_qg = (B + NW * G - 1) / (NW * G);
     const uint32_t n_cs = (words + 255) / 256;
     const uint64_t per_slab = (uint64_t)n_qg * n_cs;
     uint64_t n_slabs = target / per_slab;
@@ -478,12 +491,12 @@ pir_status launch_shared(const uint32_t* d_DB, uint32_t rows, uint32_t words, ui
     const uint64_t blocks = n_slabs * per_slab;
     if (blocks > 0x7FFFFFFFull) return PIR_ERR_SHAPE;
     const bool vec = ((uintptr_t)d_DB % 16 == 0) && (words % 4 == 0) && (pitch % 4 == 0);
-    if (EIGHT) {
+    if constexpr (NW8 != 0) {
         if (vec)
-            k_chor_shared8<G, true><<<(uint32_t)blocks, kThreads, 0, s>>>(
+            k_chor_shared8<G, NW, true><<<(uint32_t)blocks, 64 * NW, 0, s>>>(
                 d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
         else
-            k_chor_shared8<G, false><<<(uint32_t)blocks, kThreads, 0, s>>>(
+            k_chor_shared8<G, NW, false><<<(uint32_t)blocks, 64 * NW, 0, s>>>(
                 d_DB, pitch, rows, words, d_Q, qwords, B, (uint32_t)slab, n_qg, n_cs, d_out);
     } else if (vec) {
         k_chor_shared<G, true><<<(uint32_t)blocks, kThreads, 0, s>>>(
@@ -549,14 +562,22 @@ pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_
     const pir_status st = chor_init(d_out, d_init, (uint64_t)B * words, s);
     if (st != PIR_OK) return st;
     // Small batches stream every row under masks; larger ones use the
-    // 4-row tables.  Fewer, longer slabs for large batches keep the number of
+    // XOR tables.  Fewer, longer slabs for large batches keep the number of
     // output atomics down.
     if (B == 1) return launch_stream<1>(d_DB, rows, words, pitch, d_Q, B, d_out, s);
     if (B <= 4) return launch_stream<4>(d_DB, rows, words, pitch, d_Q, B, d_out, s);
     if (B <= 16) return launch_shared<4>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
     if (B <= 32) return launch_shared<8>(d_DB, rows, words, pitch, d_Q, B, d_out, 1024, s);
     if (B <= 256) return launch_shared<16>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
-    return launch_shared<32, true>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
+    // Above 256: the 8-row kernel.  Eight waves per workgroup (one per CU)
+    // share each table across 256 queries, which halves the table build per
+    // query, but pad the batch to a multiple of 256; four waves (two
+    // workgroups per CU) pad to 128.  Eight when that pads no further
+    // (measured: 1024 queries 3.33 -> 2.91 ms, 512 1.76 -> 1.60 ms; 300
+    // stays with four, 1.33 against 1.47 ms).
+    const uint32_t pad4 = (B + 127) / 128 * 128, pad8 = (B + 255) / 256 * 256;
+    if (pad8 <= pad4) return launch_shared<32, 8>(d_DB, rows, words, pitch, d_Q, B, d_out, 256, s);
+    return launch_shared<32, 4>(d_DB, rows, words, pitch, d_Q, B, d_out, 512, s);
 }
 
 extern "C" {

@@ -18,7 +18,7 @@ def qp(gpu):
 
 @pytest.mark.parametrize("rows,W", [(1, 1), (31, 3), (32, 4), (33, 768), (100, 5),
                                     (1000, 1025), (4097, 12)])
-@pytest.mark.parametrize("B", [1, 3, 5, 16, 17, 40, 300])
+@pytest.mark.parametrize("B", [1, 3, 5, 16, 17, 40, 300, 512, 700])
 def test_chor_ragged(qp, rows, W, B):
     banner(f"chor rows={rows} W={W} B={B}")
     g = np.random.default_rng(rows * 7 + W * 3 + B)
