@@ -601,11 +601,15 @@ struct Ring {
         (DX > 0 ? A_LOADS : 0) + (QX > 0 ? LOADS - A_LOADS : 0) + (STAGES - 2) * LOADS;
     // The loads of the tile that refills a freed slot are spread over all
     // KS k-steps of a stage when another tile is in flight (three or more
-    // stages), else over the fewest k-steps that fit (one load per MFMA),
-    // so the tile has the rest of the stage to land.
+    // stages, or a D ring one tile deeper, whose D tile then has two stages
+    // to land), else over the fewest k-steps that fit (one load per MFMA),
+    // so the tile has the rest of the stage to land.  (Deeper D ring, 64
+    // queries at 32768^2: 380-384 us with the loads in the first k-step,
+    // 347-357 us spread; the two-stage ring and a deeper QL ring gained
+    // nothing from spreading.)
     static constexpr int KS = BK / 32;
     static constexpr int FIT = (LOADS + TM * TN - 1) / (TM * TN);
-    static constexpr int ISSUE_STEPS = STAGES > 2 ? KS : (FIT < KS ? FIT : KS);
+    static constexpr int ISSUE_STEPS = (STAGES > 2 || DX > 0) ? KS : (FIT < KS ? FIT : KS);
     static_assert(QL_WAIT < 64, "vmcnt range");
     static_assert(STAGES >= 2, "one tile in flight while one is consumed");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
