@@ -357,6 +357,26 @@ __global__ __launch_bounds__(256) void k_finish(Epi e, uint32_t splits) {
     }
 }
 
+// The same for the mod 2^32 form, four queries per thread with 16-byte
+// partial loads and output stores (B % 4 == 0, queries contiguous and the
+// output rows 16-byte aligned): a quarter of the threads and address
+// arithmetic for a pass that only streams the partials.
+__global__ __launch_bounds__(256) void k_finish4(Epi e, uint32_t splits) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // group of 4 outputs
+    const uint32_t B4 = e.B / 4u;
+    if (g >= (uint64_t)e.M * B4) return;
+    const uint32_t i = (uint32_t)(g / B4), b = 4u * (uint32_t)(g % B4);
+    const uint32_t r = e.rows ? e.rows[i] : i;
+    if (r >= e.R) return;
+    const uint64_t plane4 = (uint64_t)e.M * B4;
+    const uint32_t rs = kCentreWord * e.rowsum[r];
+    u32x4 v = u32x4{colterm32(e, b) + rs, colterm32(e, b + 1) + rs, colterm32(e, b + 2) + rs,
+                    colterm32(e, b + 3) + rs};
+    const u32x4* part = static_cast<const u32x4*>(e.part) + g;
+    for (uint32_t s = 0; s < splits; ++s) v += part[s * plane4];
+    *reinterpret_cast<u32x4*>(e.out + (uint64_t)r * e.o_ldr + b) = v;
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
 // contiguous range of workgroup indices, so the tiles it runs at once are
 // neighbours (shared D rows and query tiles stay in its own L2).
@@ -1475,8 +1495,12 @@ pir_status mfma_run_batch(const pir_db_t* db, const BatchIO& io, uint32_t B,
     if (st != PIR_OK || P.splits <= 1) return st;
     const uint64_t n = (uint64_t)P.M * B;
     if (n == 0) return PIR_OK;
+    const bool vec4 = !exact && B % 4 == 0 && io.o_ldb == 1 && io.o_ldr % 4 == 0 &&
+                      (uintptr_t)io.out % 16 == 0;
     if (exact)
         k_finish<true><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, P.splits);
+    else if (vec4)
+        k_finish4<<<(uint32_t)((n / 4 + 255) / 256), 256, 0, s>>>(g.e, P.splits);
     else
         k_finish<false><<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(g.e, P.splits);
     PIR_LAUNCH_CHECK();
