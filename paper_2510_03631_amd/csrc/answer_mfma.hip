@@ -1128,6 +1128,11 @@ using Ring8w256x256K128Q3 = Ring<4, 2, 2, 4, 2, 128, false, 0, 1>;
 using Narrow256x32K128D4 = Ring<4, 1, 2, 1, 3, 128, true, 1>;
 using Narrow128x32K128D8 = Ring<4, 1, 1, 1, 6, 128, true, 2>;
 using Ring256x256K128S2 = Ring<2, 2, 4, 4, 2, 128>;     // 4 waves of 128 x 128, 128 KiB
+// The same with the D or the limb-plane ring one tile deeper (160 KiB): a
+// 128 x 128 wave tile reads 0.5 KiB of LDS fragments per MFMA against 0.75
+// for the 8-wave tile's 64 x 128.
+using Ring256x256K128D3 = Ring<2, 2, 4, 4, 2, 128, false, 1>;
+using Ring256x256K128Q3 = Ring<2, 2, 4, 4, 2, 128, false, 0, 1>;
 // Two workgroups per CU (64 KiB each): the waves sharing a SIMD belong to
 // different workgroups, so one's barrier does not idle the other.
 using Ring128x128K128S2 = Ring<4, 1, 1, 4, 2, 128>;
@@ -1175,6 +1180,8 @@ const VariantInfo kVariants[] = {
     {"ring8w_256x256_k128_d2q3", kRing, 256, 256, 128, launch_ring<Ring8w256x256K128Q3>},
     {"narrow_256x32_k128_d4q3", kRing, 256, 32, 128, launch_ring<Narrow256x32K128D4>, 1, true},
     {"narrow_128x32_k128_d8q6", kRing, 128, 32, 128, launch_ring<Narrow128x32K128D8>, 1, true},
+    {"ring_256x256_k128_d3q2", kRing, 256, 256, 128, launch_ring<Ring256x256K128D3>},
+    {"ring_256x256_k128_d2q3", kRing, 256, 256, 128, launch_ring<Ring256x256K128Q3>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
@@ -1361,6 +1368,8 @@ pir_status mfma_init() {
     if ((st = set_ring_lds<Ring8w256x256K128Q3>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Narrow256x32K128D4>()) != PIR_OK) return st;
     if ((st = set_ring_lds<Narrow128x32K128D8>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring256x256K128D3>()) != PIR_OK) return st;
+    if ((st = set_ring_lds<Ring256x256K128Q3>()) != PIR_OK) return st;
     if ((st = set_roles_lds<Roles256x256A5B4>()) != PIR_OK) return st;
     return set_roles_lds<Roles128x256A10B4>();
 }
