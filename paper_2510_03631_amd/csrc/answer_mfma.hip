@@ -1184,8 +1184,8 @@ const VariantInfo kVariants[] = {
     {"ring_256x256_k128_d2q3", kRing, 256, 256, 128, launch_ring<Ring256x256K128Q3>},
 };
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarRingWide = 6, kVarReg256 = 10,
-                   kVarReg128 = 11, kVarFew = 12;
+constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarReg256 = 10,
+                   kVarReg128 = 11, kVarFew = 12, kVarRing4wD3 = 23;
 
 bool ring_ok(const pir_db_t* db) { return db->aligned && (db->cols % 16 == 0); }
 
@@ -1207,12 +1207,15 @@ bool variant_valid(const pir_db_t* db, uint32_t B, uint32_t v) {
     return (4u * padded_batch(B)) % vi.bn == 0;
 }
 
-// Matrix-core choice (any batch size, gathered rows allowed).
+// Matrix-core choice (any batch size, gathered rows allowed).  From 64
+// queries up, the four-wave 256 x 256 tile with the deeper D ring
+// (ring_256x256_k128_d3q2), which led the autotuner at 64-1024 queries on
+// 32768^2, 131072^2, 65536 x 32768 and the 3072 x 2^18 field form.
 uint32_t default_gemm(const pir_db_t* db, uint32_t B) {
     const uint32_t Bp = padded_batch(B);
     if (!ring_ok(db)) return Bp == 32u ? kVarReg128 : kVarReg256;
     if (Bp == 32u) return kVarRing128;
-    return Bp >= 256u ? kVarRingWide : kVarRing256;
+    return kVarRing4wD3;
 }
 
 // The dot4 stream beats the padded matrix-core tile up to two queries; at
