@@ -1,6 +1,6 @@
 """Build ``tests/native/server_stress``: the serving-loop stress check.
 
-The library's sources and the driver are compiled with a sanitizer on their
+The library's sources and the stress program are compiled with a sanitizer on their
 host code only (``-Xarch_host`` before the sanitizer flag; the gfx950 device
 code is built as for the library), and linked with the C oracle (built
 without OpenMP, so its loops run on the calling thread).  Objects go to
