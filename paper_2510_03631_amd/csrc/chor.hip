@@ -570,7 +570,22 @@ pir_status chor_xor(const uint32_t* d_DB, uint32_t rows, uint32_t words, uint64_
     if (B <= 4) return launch_stream<4>(d_DB, rows, words, pitch, d_Q, B, d_out, s);
     if (B <= 16) return launch_shared<4>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
     if (B <= 32) return launch_shared<8>(d_DB, rows, words, pitch, d_Q, B, d_out, 1024, s);
-    if (B <= 256) return launch_shared<16>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
+    if (B <= 256) {
+        // Groups of 16: the 8-row kernel with eight waves (128 queries per
+        // table) when that pads the batch no further than the 4-row
+        // kernel's 64 per workgroup and its slabs keep at least 1024 rows;
+        // shorter slabs spend the time in their output atomics.  Measured
+        // on 2^18 rows of 3 KB: 128 queries 680 -> 654 us, 200 1155 ->
+        // 1017 us, 256 1188 -> 1086 us; 64 stays with the 4-row kernel (400
+        // against 543 us), and so does the CIP-PIR flip chunk of 2^16 rows
+        // (128 queries 246 against 335 us, 256 362 against 428 us).
+        const uint32_t pad64 = (B + 63) / 64 * 64, pad128 = (B + 127) / 128 * 128;
+        const uint64_t per_slab8 = (uint64_t)(pad128 / 128) * ((words + 255) / 256);
+        const uint64_t slabs8 = per_slab8 >= 768 ? 1 : 768 / per_slab8;
+        if (pad128 <= pad64 && rows / slabs8 >= 1024)
+            return launch_shared<16, 8>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
+        return launch_shared<16>(d_DB, rows, words, pitch, d_Q, B, d_out, 768, s);
+    }
     // Above 256: the 8-row kernel.  Eight waves per workgroup (one per CU)
     // share each table across 256 queries, which halves the table build per
     // query, but pad the batch to a multiple of 256; four waves (two

@@ -18,7 +18,7 @@ def qp(gpu):
 
 @pytest.mark.parametrize("rows,W", [(1, 1), (31, 3), (32, 4), (33, 768), (100, 5),
                                     (1000, 1025), (4097, 12)])
-@pytest.mark.parametrize("B", [1, 3, 5, 16, 17, 40, 300, 512, 700])
+@pytest.mark.parametrize("B", [1, 3, 5, 16, 17, 40, 100, 150, 200, 300, 512, 700])
 def test_chor_ragged(qp, rows, W, B):
     banner(f"chor rows={rows} W={W} B={B}")
     g = np.random.default_rng(rows * 7 + W * 3 + B)
@@ -59,7 +59,7 @@ def test_chor_reconstruction_on_device(qp):
     assert np.array_equal(resp[0] ^ resp[1] ^ resp[2], DB[theta])
 
 
-@pytest.mark.parametrize("B", [1, 128, 1024])
+@pytest.mark.parametrize("B", [1, 128, 200, 1024])
 def test_chor_paper_scale(qp, B):
     """2^18 entries of 3 KB (768 MiB), batches of 1, 2^7 and 2^10 queries."""
     banner(f"chor 2^18 x 3KB, B={B}")
