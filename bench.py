@@ -505,12 +505,12 @@ def serving_bench(args) -> dict:
            "budget_bytes": budget, "max_batch": 64, "slots_per_db": 3,
            "max_inflight": inflight, "p99_bound_ms": p99_bound}
 
-    def sweep(srv, rates, seed_off):
+    def sweep(srv, rates, seed_off, long_from):
         runs = []
         for rate in rates:
             # Rates near saturation run longer: a stall there turns into a
             # queue, and a short window can miss it.
-            t, w, qs = trace(rate, 5.0 if rate >= 200000.0 else 2.0, int(rate) + seed_off)
+            t, w, qs = trace(rate, 5.0 if rate >= long_from else 2.0, int(rate) + seed_off)
             runs.append(serving_run(srv, t, w, qs))
             log(f"serving sweep: {rate:.0f} q/s offered, p99 {runs[-1]['p99_ms']} ms")
             if runs[-1]["p99_ms"] > p99_bound:
@@ -535,11 +535,13 @@ def serving_bench(args) -> dict:
         out["at_2000qps"]["window_s"] = args.serving_seconds
         out["batched_sweep"], out["batched_max_qps_at_p99_bound"] = sweep(
             srv, (8000.0, 20000.0, 40000.0, 80000.0, 160000.0, 240000.0, 320000.0, 360000.0,
-                  400000.0, 440000.0, 480000.0), 0)
+                  400000.0, 440000.0, 480000.0), 0, 200000.0)
     with Server(dbs, max_batch=1, slots_per_db=3, mem_budget_bytes=budget,
                 max_inflight=inflight) as srv:
+        # One query per launch saturates near 16k q/s: finer, longer steps
+        # from 12k on.
         out["plain_sweep"], out["plain_max_qps_at_p99_bound"] = sweep(
-            srv, (2000.0, 8000.0, 16000.0, 20000.0), 1)
+            srv, (2000.0, 8000.0, 12000.0, 14000.0, 16000.0, 18000.0, 20000.0), 1, 12000.0)
     for db in dbs:
         db.close()
     return out
