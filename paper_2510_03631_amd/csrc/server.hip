@@ -413,13 +413,18 @@ struct pir_server {
                     cv_done.notify_all();
                 }
             }
-            // Spin briefly for low completion latency, then back off.
+            // Batches are in flight: yield-spin for low completion latency
+            // for up to 2 ms after the last completion, longer than one
+            // query's scan of a 2 GiB database (about 0.33 ms), then back
+            // off to 20 us sleeps, which overshoot by tens of microseconds.
+            // (2000 q/s on the eight regional databases: p99 0.44-0.45 ms
+            // with a 0.2 ms spin, 0.42 ms with 2 ms.)
             if (any) {
                 idle_since = 0;
             } else {
                 const uint64_t t = now_ns();
                 if (!idle_since) idle_since = t;
-                if (t - idle_since < 200000) std::this_thread::yield();
+                if (t - idle_since < 2000000) std::this_thread::yield();
                 else std::this_thread::sleep_for(std::chrono::microseconds(20));
             }
         }
