@@ -1156,7 +1156,7 @@ struct VariantInfo {
     bool narrow;            // narrow QL layout: all queries in one column tile
 };
 
-const VariantInfo kVariants[] = {
+constexpr VariantInfo kVariants[] = {
     {"auto", kAuto, 0, 0, 0, nullptr},
     {"ring_128x128_s8", kRing, 128, 128, 64, launch_ring<Ring128x128S8>},
     {"ring_128x128_k128_s4", kRing, 128, 128, 128, launch_ring<Ring128x128K128S4>},
@@ -1186,6 +1186,17 @@ const VariantInfo kVariants[] = {
 constexpr uint32_t kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr uint32_t kVarRing128 = 2, kVarRing256 = 4, kVarReg256 = 10,
                    kVarReg128 = 11, kVarFew = 12, kVarRing4wD3 = 23;
+constexpr bool same_name(const char* a, const char* b) {
+    return *a == *b && (*a == '\0' || same_name(a + 1, b + 1));
+}
+// The built-in choices name table rows by index: keep them on their rows.
+static_assert(same_name(kVariants[kVarRing128].name, "ring_128x128_k128_s4") &&
+                  same_name(kVariants[kVarRing256].name, "ring8w_128x256_k128_s3") &&
+                  same_name(kVariants[kVarReg256].name, "reg_128x256") &&
+                  same_name(kVariants[kVarReg128].name, "reg_128x128") &&
+                  same_name(kVariants[kVarFew].name, "few") &&
+                  same_name(kVariants[kVarRing4wD3].name, "ring_256x256_k128_d3q2"),
+              "default variant indices");
 
 bool ring_ok(const pir_db_t* db) { return db->aligned && (db->cols % 16 == 0); }
 
