@@ -477,7 +477,10 @@ pir_status pir_server_create(const pir_server_config* cfg, pir_server_t** out);
 pir_status pir_server_add_db(pir_server_t* server, pir_db_t* db, uint32_t* db_index);
 /* Allocate slots, capture the graphs and start the scheduler and completion
  * threads.  PIR_ERR_NO_MEMORY if a single query of some database does not
- * fit the budget or an allocation fails. */
+ * fit the budget or an allocation fails.  While batches are in flight the
+ * completion thread polls them, yielding between polls, for up to 2 ms after
+ * the last completion (then every 20 us), so it keeps one host core busy
+ * under load; with nothing in flight it sleeps. */
 pir_status pir_server_start(pir_server_t* server);
 /*
  * Queue one query (C words, host memory) for database `db_index`.  The
